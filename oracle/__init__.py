@@ -1,0 +1,254 @@
+"""CPU oracle for the recursive hypot-based norms -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py``
+may import this package.  It shares no code with the GPU library.
+
+Library contract applied on top of the paper's recursions (the paper's theorems
+assume finite inputs; this is the build's reading): n <= 0 gives 0; any NaN input
+gives NaN; otherwise any infinite input gives +inf; otherwise the recursion runs
+(and may overflow to +inf).
+
+Algorithms (paper: Novakovic, arXiv 2509.06220):
+  'A'  R with cr_hypot (Sect. 2, Listing 1, Table 2)        -- the parity oracle
+  'H'  R with v1_hypot (Listing 2)
+  'Z'  Z with P lanes and the v1 node, then A (Sect. 3, Listing 4; the recommended xNRMF)
+p-norms: R (or Z) with the Listing 5 node v1_lp using a correctly rounded pow;
+p = 1 -> sumabs (Eq. vp1); p = inf or p >= cutoff (2^53 D, 2^24 S) -> maxabs (Eq. vpI).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+from . import bounds, exact  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(_HERE, "libvnp_oracle.so")
+SRC = os.path.join(_HERE, "vnp_oracle.c")
+
+CFLAGS = ["-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-std=gnu11"]
+LIBS = ["-lquadmath", "-lm", "-ldl"]
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (no SIMD options, no fast-math)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, SRC, "-o", tmp, *LIBS])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(LIB)
+        d, f, i64, i, vp = ctypes.c_double, ctypes.c_float, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
+        sig = {
+            "vnpo_cr_hypot": (d, [d, d]),
+            "vnpo_cr_hypotf": (f, [f, f]),
+            "vnpo_v1_hypot": (d, [d, d]),
+            "vnpo_v1_hypotf": (f, [f, f]),
+            "vnpo_cr_pow": (d, [d, d]),
+            "vnpo_cr_powf": (f, [f, f]),
+            "vnpo_v1_lp": (d, [d, d, d]),
+            "vnpo_v1_lpf": (f, [f, f, f]),
+            "vnpo_dnrmf_R": (d, [i64, vp, i, i]),
+            "vnpo_snrmf_R": (f, [i64, vp, i, i]),
+            "vnpo_dnrmp_R": (d, [i64, vp, d, i]),
+            "vnpo_snrmp_R": (f, [i64, vp, f, i]),
+            "vnpo_dnrmf_Z": (d, [i64, vp, i, i, i]),
+            "vnpo_snrmf_Z": (f, [i64, vp, i, i, i]),
+            "vnpo_dnrmp_Z": (d, [i64, vp, d, i, i]),
+            "vnpo_snrmp_Z": (f, [i64, vp, f, i, i]),
+            "vnpo_trace": (i64, [i64, i, vp]),
+            "vnpo_sumsq_exact": (i, [i64, vp, i, vp, i]),
+            "vnpo_sa_limbs": (i, []),
+            "vnpo_sa_bias": (i, []),
+            "vnpo_pnorm_quad": (None, [i64, vp, i, d, i, vp, vp]),
+            "vnpo_powq2": (None, [d, d, vp, vp]),
+            "vnpo_pow_ambiguous": (i64, []),
+            "vnpo_pow_unresolved": (i64, []),
+            "vnpo_mpfr_pow": (d, [d, d, i]),
+            "vnpo_exact_failures": (i64, []),
+            "vnpo_reset_counters": (None, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def default_threads() -> int:
+    return max(1, min(os.cpu_count() or 1, 16))
+
+
+# ---------------------------------------------------------------- scalar nodes
+def cr_hypot(x, y):
+    return _L().vnpo_cr_hypot(float(x), float(y))
+
+
+def cr_hypotf(x, y):
+    return float(np.float32(_L().vnpo_cr_hypotf(float(x), float(y))))
+
+
+def v1_hypot(x, y):
+    return _L().vnpo_v1_hypot(float(x), float(y))
+
+
+def v1_hypotf(x, y):
+    return float(np.float32(_L().vnpo_v1_hypotf(float(x), float(y))))
+
+
+def cr_pow(x, y):
+    return _L().vnpo_cr_pow(float(x), float(y))
+
+
+def cr_powf(x, y):
+    return float(np.float32(_L().vnpo_cr_powf(float(x), float(y))))
+
+
+def v1_lp(p, x, y):
+    return _L().vnpo_v1_lp(float(p), float(x), float(y))
+
+
+def v1_lpf(p, x, y):
+    return float(np.float32(_L().vnpo_v1_lpf(float(p), float(x), float(y))))
+
+
+def powq(x, y):
+    """binary128 x^y as an exact hi + lo pair of doubles (for pinning the pow evaluation)."""
+    hi, lo = ctypes.c_double(), ctypes.c_double()
+    _L().vnpo_powq2(float(x), float(y), ctypes.byref(hi), ctypes.byref(lo))
+    return hi.value, lo.value
+
+
+def mpfr_pow(x, y, prec=53):
+    """GNU MPFR's correctly rounded pow (the oracle's fallback), for pinning cr_pow."""
+    return _L().vnpo_mpfr_pow(float(x), float(y), int(prec))
+
+
+def counters():
+    L = _L()
+    return {"pow_ambiguous": L.vnpo_pow_ambiguous(), "pow_unresolved": L.vnpo_pow_unresolved(),
+            "exact_failures": L.vnpo_exact_failures()}
+
+
+def reset_counters():
+    _L().vnpo_reset_counters()
+
+
+# ---------------------------------------------------------------- norms
+def _prep(x):
+    x = np.ascontiguousarray(x)
+    if x.dtype not in (np.float64, np.float32):
+        raise TypeError(x.dtype)
+    return x
+
+
+def _contract(x):
+    """Returns the contract's value for empty / non-finite inputs, else None."""
+    if x.size == 0:
+        return x.dtype.type(0.0)
+    if not np.all(np.isfinite(x)):
+        if np.any(np.isnan(x)):
+            return x.dtype.type(np.nan)
+        return x.dtype.type(np.inf)
+    return None
+
+
+def nrmf(x, algo: str = "A", lanes: int | None = None, sort: bool = False, threads: int | None = None):
+    """Frobenius norm by the paper's algorithm ``algo`` ('A', 'H' or 'Z')."""
+    x = _prep(x)
+    c = _contract(x)
+    if c is not None:
+        return c
+    L = _L()
+    t = threads or default_threads()
+    single = x.dtype == np.float32
+    n = x.size
+    if algo in ("A", "H"):
+        node = 0 if algo == "A" else 1
+        fn = L.vnpo_snrmf_R if single else L.vnpo_dnrmf_R
+        return x.dtype.type(fn(n, x.ctypes.data, node, t))
+    if algo == "Z":
+        P = lanes or (16 if single else 8)
+        fn = L.vnpo_snrmf_Z if single else L.vnpo_dnrmf_Z
+        return x.dtype.type(fn(n, x.ctypes.data, P, int(sort), t))
+    raise ValueError(algo)
+
+
+def nrmp(x, p: float, algo: str = "A", lanes: int | None = None, threads: int | None = None):
+    """p-norm by the paper's recursion with the Listing 5 node ('A' = R, 'Z' = Z + A)."""
+    x = _prep(x)
+    if not (p > 0):
+        raise ValueError("p must be > 0")
+    c = _contract(x)
+    if c is not None:
+        return c
+    L = _L()
+    t = threads or default_threads()
+    single = x.dtype == np.float32
+    n = x.size
+    if algo == "A":
+        fn = L.vnpo_snrmp_R if single else L.vnpo_dnrmp_R
+        return x.dtype.type(fn(n, x.ctypes.data, p, t))
+    if algo == "Z":
+        P = lanes or (16 if single else 8)
+        fn = L.vnpo_snrmp_Z if single else L.vnpo_dnrmp_Z
+        return x.dtype.type(fn(n, x.ctypes.data, p, P, t))
+    raise ValueError(algo)
+
+
+def trace(n: int, lanes: int = 0):
+    """Tree shape: list of (left, right) ids per node in completion order.
+
+    Leaves are 1..n; the k-th node (0-based) has id 1000000 + k."""
+    buf = np.zeros(2 * max(n + lanes, 1), dtype=np.int64)
+    k = _L().vnpo_trace(n, lanes, buf.ctypes.data)
+    return [(int(buf[2 * i]), int(buf[2 * i + 1])) for i in range(k)]
+
+
+def exact_nrm2(x, threads: int | None = None):
+    """RN(sqrt(sum x_i^2)) exactly: superaccumulated squares + exact integer square root."""
+    x = _prep(x)
+    c = _contract(x)
+    if c is not None:
+        return c
+    L = _L()
+    nl = L.vnpo_sa_limbs()
+    limbs = np.zeros(nl, dtype=np.uint64)
+    L.vnpo_sumsq_exact(x.size, x.ctypes.data, int(x.dtype == np.float32), limbs.ctypes.data,
+                       threads or default_threads())
+    N = exact.limbs_to_int(limbs)
+    fmt = "f32" if x.dtype == np.float32 else "f64"
+    return x.dtype.type(exact.rn_sqrt_dyadic(N, -L.vnpo_sa_bias(), fmt))
+
+
+def ref_pnorm(x, p: float, threads: int | None = None):
+    """binary128 reference (sum |x_i|^p)^(1/p) as (hi, lo) doubles (error ~1e-25 relative)."""
+    x = _prep(x)
+    hi, lo = ctypes.c_double(), ctypes.c_double()
+    _L().vnpo_pnorm_quad(x.size, x.ctypes.data, int(x.dtype == np.float32), float(p),
+                         threads or default_threads(), ctypes.byref(hi), ctypes.byref(lo))
+    return hi.value, lo.value
+
+
+def relerr(approx, ref, fmt: str) -> float:
+    """Eq. (relerr): |ref - approx| / (ref * eps), ref rounded to the working precision."""
+    e = 2.0 ** -53 if fmt == "f64" else 2.0 ** -24
+    ref = float(ref)
+    approx = float(approx)
+    if ref == 0:
+        return 0.0 if approx == 0 else math.inf
+    return abs(ref - approx) / (ref * e)
