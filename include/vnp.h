@@ -1,0 +1,140 @@
+/*
+ * vnp -- recursive hypot-based vector norms on AMD Instinct MI355X (gfx950).
+ *
+ * Method: V. Novakovic, "Recursive vectorized computation of the vector p-norm"
+ * (arXiv 2509.06220).  The Frobenius norm of x (Sect. 1, Eq. (12I)) is computed by a
+ * pairwise tree whose every node combines two partial norms with a hypotenuse (Eq. (hr):
+ * ||x|| = hypot(||x_I||, ||x_J||) for any split into disjoint parts I, J); the p-norm
+ * (Eq. (p)) by the same tree with the node M (1 + (m/M)^p)^(1/p) (Sect. 4, Eq. (sp)).
+ *
+ * The tree is fixed by the logical index alone (a perfect binary tree over a fixed
+ * bit order, zero-padded), so every result is bitwise reproducible across runs, grid
+ * and block shapes, pointer alignment, plain / batched / served calls and streams.
+ * vnp_tree_id() names the tree and node; results are bitwise comparable only within
+ * one tree id.  The paper's own vector algorithms have the same property for a fixed
+ * vector width (Sect. 3).
+ *
+ * Conventions for every call:
+ *   - Pointers named x, offsets, res, ... are DEVICE pointers owned by the caller
+ *     (res may also be host-mapped pinned memory).  The library never frees or keeps
+ *     them, never writes to x, and accesses them only from work enqueued on `stream`.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  All calls are
+ *     asynchronous and stream-ordered; results are visible after the stream completes.
+ *   - Return value, LAPACK INFO style: 0 = success; -k = argument k is invalid (nothing
+ *     is enqueued); > 0 = a HIP runtime error code.  Errors of earlier asynchronous work
+ *     surface at the next synchronization, not here.  Nothing aborts or throws across
+ *     the ABI.
+ *   - n <= 0 (or nseg segments of length 0) give a result of +0.
+ *   - Special values: any NaN element gives NaN; otherwise any infinite element gives
+ *     +inf; otherwise the tree result, which is +inf only if the norm overflows.
+ *   - Calls on different streams may run concurrently; each (device, stream) pair gets
+ *     its own workspace, created on first use and released by vnp_finalize().
+ */
+#ifndef VNP_H
+#define VNP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VNP_VERSION_MAJOR 0
+#define VNP_VERSION_MINOR 1
+
+/* Data types. */
+#define VNP_F64 0
+#define VNP_F32 1
+
+/* Status codes beyond the INFO convention. */
+#define VNP_OK 0
+#define VNP_EAGAIN 100000 /* resource temporarily exhausted (server pool full) */
+#define VNP_ENOTFOUND 100001 /* unknown ticket */
+#define VNP_EPENDING 100002 /* ticket not complete yet */
+
+/* ------------------------------------------------------------------------------------
+ * Single vector.  Paper: xNRMF (Sect. 1; the recommended algorithm of Sect. 3) and
+ * xNRMP (Sect. 4), over n elements with the BLAS stride convention of xNRM2 (Sect. 3):
+ * logical element i (0 <= i < n) is x[i * incx] for incx >= 1 and
+ * x[(n - 1 - i) * (-incx)] for incx <= -1.  incx == 0 is invalid (-3).
+ * The result is written to *res (one element of the working precision).
+ * Errors: n > VNP_MAX_N -> -1; x == NULL with n > 0 -> -2; incx == 0 -> -3;
+ * p <= 0 or NaN -> -4 (nrmp only); res == NULL -> -4 (nrmf) / -5 (nrmp).
+ * ---------------------------------------------------------------------------------- */
+#define VNP_MAX_N (((int64_t)1) << 40)
+
+int vnp_dnrmf(int64_t n, const double *x, int64_t incx, double *res, void *stream);
+int vnp_snrmf(int64_t n, const float *x, int64_t incx, float *res, void *stream);
+
+/* p-norm.  p = 1 uses |a| + |b| nodes (Eq. (vp1)); p = +inf, and p at or above the
+ * cutoff of Sect. 4 (2^53 for D, 2^24 for S), use max(|a|, |b|) (Eq. (vpI)); p = 2 uses
+ * the Frobenius node; other p > 0 use the node of Listing 5 (0 < p < 1 gives the
+ * quasi-norm of Sect. 4). */
+int vnp_dnrmp(int64_t n, const double *x, int64_t incx, double p, double *res, void *stream);
+int vnp_snrmp(int64_t n, const float *x, int64_t incx, float p, float *res, void *stream);
+
+/* ------------------------------------------------------------------------------------
+ * Batched segments in one launch.  Paper: norms of the columns of a multi-dimensional
+ * array, then combined (Sect. 3.1).  Segment s is x[offsets[s] .. offsets[s+1]) (device
+ * int64 array of nseg + 1 non-decreasing entries, offsets[0] >= 0); its norm goes to
+ * res[s].  Each segment's result is bitwise equal to the single-vector call on it.
+ * Errors: nseg < 0 -> -1; offsets == NULL -> -2; x == NULL -> -3; res == NULL -> -4
+ * (dnrmp_batched: p invalid -> -4, res == NULL -> -5).  Offsets are not validated on
+ * the device beyond clamping lengths at 0; out-of-range offsets are undefined behaviour.
+ * ---------------------------------------------------------------------------------- */
+int vnp_dnrmf_batched(int64_t nseg, const int64_t *offsets, const double *x, double *res, void *stream);
+int vnp_snrmf_batched(int64_t nseg, const int64_t *offsets, const float *x, float *res, void *stream);
+int vnp_dnrmp_batched(int64_t nseg, const int64_t *offsets, const double *x, double p, double *res, void *stream);
+int vnp_snrmp_batched(int64_t nseg, const int64_t *offsets, const float *x, float p, float *res, void *stream);
+
+/* Column norms of an m x ncols column-major matrix with leading dimension lda >= m
+ * (Sect. 3.1): res[j] = ||A(:, j)||.  Errors: m < 0 -> -1; ncols < 0 -> -2; A == NULL ->
+ * -3; lda < max(1, m) -> -4; res == NULL -> -5. */
+int vnp_dnrmf_cols(int64_t m, int64_t ncols, const double *A, int64_t lda, double *res, void *stream);
+int vnp_snrmf_cols(int64_t m, int64_t ncols, const float *A, int64_t lda, float *res, void *stream);
+
+/* ------------------------------------------------------------------------------------
+ * Plans: a batched workload captured once into a HIP graph with launch shapes chosen
+ * by the autotuner (which never changes results), then replayed.  The plan owns its
+ * workspace; the caller's buffers must stay valid while the plan is used.
+ * ---------------------------------------------------------------------------------- */
+typedef struct vnp_plan vnp_plan;
+
+typedef struct {
+    int dtype;               /* VNP_F64 or VNP_F32 */
+    double p;                /* 2.0 for the Frobenius norm */
+    int64_t nseg;            /* number of segments */
+    const int64_t *offsets;  /* device, nseg + 1 entries */
+    const int64_t *h_offsets;/* optional host copy of offsets (enables load balancing) */
+    const void *x;           /* device data */
+    void *res;               /* device results, nseg elements */
+    int autotune;            /* 1: time candidate shapes on `stream` during creation */
+} vnp_plan_desc;
+
+int vnp_plan_create(vnp_plan **plan, const vnp_plan_desc *desc, void *stream);
+int vnp_plan_exec(vnp_plan *plan, void *stream);
+int vnp_plan_destroy(vnp_plan *plan);
+/* Chosen launch shape: blocks, waves per block, tiles per work item. */
+int vnp_plan_info(const vnp_plan *plan, int *blocks, int *waves, int *tiles_per_item);
+
+/* ------------------------------------------------------------------------------------
+ * Library information.
+ * ---------------------------------------------------------------------------------- */
+const char *vnp_version(void);
+/* 32-bit id of the canonical tree and node for a dtype (VNP_F64 / VNP_F32). */
+uint32_t vnp_tree_id(int dtype);
+/* Elements per tile of the canonical tree for a dtype. */
+int64_t vnp_tile_elems(int dtype);
+/* Release per-stream workspaces of the current device.  Not thread-safe with calls
+ * in flight. */
+int vnp_finalize(void);
+
+/* Launch-shape override for tests and tuning: waves per block and tiles per wave
+ * (powers of two; 0 = automatic).  Results never depend on it.  Process-wide. */
+int vnp_set_launch_shape(int waves_per_block, int tiles_per_wave);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VNP_H */

@@ -1,0 +1,190 @@
+"""vnp: recursive hypot-based vector norms on AMD MI355X (gfx950).
+
+Thin ctypes binding over the C ABI in ``include/vnp.h`` (``libvnp.so``, built in-tree by
+``paper_2509_06220_amd/build.py``).  Only argument marshalling happens here: torch
+supplies device memory and the current HIP stream; every step of the computation runs
+in the library's kernels.  If the library is missing the import of any entry point
+fails loudly -- there is no fallback.
+
+Method: Novakovic, "Recursive vectorized computation of the vector p-norm"
+(arXiv 2509.06220): xNRMF (Sect. 1, 3) and xNRMP (Sect. 4).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvnp.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "vnp.h")
+
+F64, F32 = 0, 1
+EAGAIN, ENOTFOUND, EPENDING = 100000, 100001, 100002
+
+
+class VnpError(RuntimeError):
+    def __init__(self, fn, code):
+        super().__init__(f"{fn} failed with status {code}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libvnp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(there is no non-HIP implementation)")
+        L = ctypes.CDLL(LIB_PATH)
+        i64, vp, d, f, i = ctypes.c_int64, ctypes.c_void_p, ctypes.c_double, ctypes.c_float, ctypes.c_int
+        sig = {
+            "vnp_dnrmf": [i64, vp, i64, vp, vp],
+            "vnp_snrmf": [i64, vp, i64, vp, vp],
+            "vnp_dnrmp": [i64, vp, i64, d, vp, vp],
+            "vnp_snrmp": [i64, vp, i64, f, vp, vp],
+            "vnp_dnrmf_batched": [i64, vp, vp, vp, vp],
+            "vnp_snrmf_batched": [i64, vp, vp, vp, vp],
+            "vnp_dnrmp_batched": [i64, vp, vp, d, vp, vp],
+            "vnp_snrmp_batched": [i64, vp, vp, f, vp, vp],
+            "vnp_dnrmf_cols": [i64, i64, vp, i64, vp, vp],
+            "vnp_snrmf_cols": [i64, i64, vp, i64, vp, vp],
+            "vnp_set_launch_shape": [i, i],
+            "vnp_finalize": [],
+        }
+        for name, args in sig.items():
+            if hasattr(L, name):
+                fn = getattr(L, name)
+                fn.argtypes = args
+                fn.restype = ctypes.c_int
+        L.vnp_version.restype = ctypes.c_char_p
+        L.vnp_version.argtypes = []
+        L.vnp_tree_id.restype = ctypes.c_uint32
+        L.vnp_tree_id.argtypes = [ctypes.c_int]
+        L.vnp_tile_elems.restype = ctypes.c_int64
+        L.vnp_tile_elems.argtypes = [ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+def header_functions():
+    """Names of the functions declared in include/vnp*.h."""
+    names = []
+    inc = os.path.dirname(HEADER)
+    for fn in sorted(os.listdir(inc)):
+        if fn.startswith("vnp") and fn.endswith(".h"):
+            with open(os.path.join(inc, fn)) as f:
+                txt = re.sub(r"/\*.*?\*/", "", f.read(), flags=re.S)
+            names += re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(vnp_[a-z0-9_]+)\s*\(", txt, re.M)
+    return names
+
+
+def _check(name, rc):
+    if rc != 0:
+        raise VnpError(name, rc)
+
+
+def _stream(t, stream):
+    import torch
+
+    if stream is not None:
+        return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def _prep_vector(x, n, incx):
+    import torch
+
+    if not x.is_cuda:
+        raise ValueError("x must be a device tensor")
+    if x.dtype not in (torch.float64, torch.float32):
+        raise TypeError(f"unsupported dtype {x.dtype}")
+    if not x.is_contiguous():
+        raise ValueError("pass the underlying contiguous storage and use incx for strides")
+    if incx == 0:
+        raise ValueError("incx must be nonzero")
+    if n is None:
+        n = (x.numel() + abs(incx) - 1) // abs(incx)
+    if n > 0 and (n - 1) * abs(incx) >= x.numel():
+        raise ValueError("n and incx reach past the end of x")
+    return n
+
+
+def nrmf(x, n=None, incx=1, out=None, stream=None):
+    """Frobenius norm of the n elements x[0], x[incx], ... (BLAS stride rules)."""
+    import torch
+
+    n = _prep_vector(x, n, incx)
+    if out is None:
+        out = torch.empty((), dtype=x.dtype, device=x.device)
+    fn = "vnp_dnrmf" if x.dtype == torch.float64 else "vnp_snrmf"
+    _check(fn, getattr(lib(), fn)(n, x.data_ptr(), incx, out.data_ptr(), _stream(x, stream)))
+    return out
+
+
+def nrmp(x, p, n=None, incx=1, out=None, stream=None):
+    """p-norm (p > 0; p = inf allowed) of the n elements x[0], x[incx], ..."""
+    import torch
+
+    n = _prep_vector(x, n, incx)
+    if out is None:
+        out = torch.empty((), dtype=x.dtype, device=x.device)
+    fn = "vnp_dnrmp" if x.dtype == torch.float64 else "vnp_snrmp"
+    _check(fn, getattr(lib(), fn)(n, x.data_ptr(), incx, float(p), out.data_ptr(), _stream(x, stream)))
+    return out
+
+
+def nrm_batched(x, offsets, p=2.0, out=None, stream=None):
+    """Norms of the segments x[offsets[s]:offsets[s+1]] in one launch (offsets: device int64)."""
+    import torch
+
+    nseg = offsets.numel() - 1
+    if out is None:
+        out = torch.empty(max(nseg, 0), dtype=x.dtype, device=x.device)
+    if offsets.dtype != torch.int64 or not offsets.is_cuda:
+        raise TypeError("offsets must be a device int64 tensor")
+    d = x.dtype == torch.float64
+    s = _stream(x, stream)
+    if p == 2.0:
+        fn = "vnp_dnrmf_batched" if d else "vnp_snrmf_batched"
+        rc = getattr(lib(), fn)(nseg, offsets.data_ptr(), x.data_ptr(), out.data_ptr(), s)
+    else:
+        fn = "vnp_dnrmp_batched" if d else "vnp_snrmp_batched"
+        rc = getattr(lib(), fn)(nseg, offsets.data_ptr(), x.data_ptr(), float(p), out.data_ptr(), s)
+    _check(fn, rc)
+    return out
+
+
+def nrmf_cols(A, m, ncols, lda, out=None, stream=None):
+    """Column norms of the column-major m x ncols matrix stored in A with leading dimension lda."""
+    import torch
+
+    if out is None:
+        out = torch.empty(ncols, dtype=A.dtype, device=A.device)
+    fn = "vnp_dnrmf_cols" if A.dtype == torch.float64 else "vnp_snrmf_cols"
+    _check(fn, getattr(lib(), fn)(m, ncols, A.data_ptr(), lda, out.data_ptr(), _stream(A, stream)))
+    return out
+
+
+def set_launch_shape(waves_per_block=0, tiles_per_wave=0):
+    """Force a launch shape (tests / tuning); (0, 0) restores the automatic choice."""
+    _check("vnp_set_launch_shape", lib().vnp_set_launch_shape(waves_per_block, tiles_per_wave))
+
+
+def tree_id(dtype=F64):
+    return lib().vnp_tree_id(dtype)
+
+
+def tile_elems(dtype=F64):
+    return lib().vnp_tile_elems(dtype)
+
+
+def version():
+    return lib().vnp_version().decode()
+
+
+def finalize():
+    _check("vnp_finalize", lib().vnp_finalize())

@@ -1,0 +1,90 @@
+// Node objects evaluated by the tree kernels.  Each provides
+//   leaf(a, b):  the node on two raw elements (signs allowed),
+//   node(a, b):  the node on two non-negative partial norms,
+//   finish(r):   the map from the tree root to the result (identity for all nodes here).
+// Paper (Novakovic, arXiv 2509.06220): Frobenius node = hypot (Sect. 1, Eq. (hr));
+// p = 1 node = |a| + |b| (Eq. (vp1)); p = infinity node = max(|a|, |b|) (Eq. (vpI)),
+// the absolute values being needed only at the lowest level (Sect. 4).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vnp_node.hpp"
+#include "vnp_tree.hpp"
+
+namespace vnp {
+
+template <typename T>
+struct HypNode;
+
+template <>
+struct HypNode<double> {
+    using T = double;
+    __device__ double leaf(double a, double b) const { return hyp_d_leaf(a, b); }
+    __device__ double node(double a, double b) const { return hyp_d(a, b); }
+    __device__ double finish(double r) const { return r; }
+};
+
+template <>
+struct HypNode<float> {
+    using T = float;
+    __device__ float leaf(float a, float b) const { return hyp_s_leaf(a, b); }
+    __device__ float node(float a, float b) const { return hyp_s(a, b); }
+    __device__ float finish(float r) const { return r; }
+};
+
+template <typename T>
+struct SumNode;
+
+template <>
+struct SumNode<double> {
+    using T = double;
+    __device__ double leaf(double a, double b) const { return __builtin_fabs(a) + __builtin_fabs(b); }
+    __device__ double node(double a, double b) const { return a + b; }
+    __device__ double finish(double r) const { return r; }
+};
+
+template <>
+struct SumNode<float> {
+    using T = float;
+    __device__ float leaf(float a, float b) const { return __builtin_fabsf(a) + __builtin_fabsf(b); }
+    __device__ float node(float a, float b) const { return a + b; }
+    __device__ float finish(float r) const { return r; }
+};
+
+// max on non-negative values through their bit patterns: the integer order equals the
+// numeric order, and NaN patterns (with the sign cleared) sort above +inf, so a NaN
+// propagates to the root.
+template <typename T>
+struct MaxNode;
+
+template <>
+struct MaxNode<double> {
+    using T = double;
+    __device__ static double mx(double a, double b)
+    {
+        const uint64_t ia = (uint64_t)__double_as_longlong(a), ib = (uint64_t)__double_as_longlong(b);
+        return __longlong_as_double((long long)(ia > ib ? ia : ib));
+    }
+    __device__ double leaf(double a, double b) const { return mx(__builtin_fabs(a), __builtin_fabs(b)); }
+    __device__ double node(double a, double b) const { return mx(a, b); }
+    __device__ double finish(double r) const { return r; }
+};
+
+template <>
+struct MaxNode<float> {
+    using T = float;
+    __device__ static float mx(float a, float b)
+    {
+        const uint32_t ia = __float_as_uint(a), ib = __float_as_uint(b);
+        return __uint_as_float(ia > ib ? ia : ib);
+    }
+    __device__ float leaf(float a, float b) const { return mx(__builtin_fabsf(a), __builtin_fabsf(b)); }
+    __device__ float node(float a, float b) const { return mx(a, b); }
+    __device__ float finish(float r) const { return r; }
+};
+
+int release_workspaces();
+int set_launch_shape(int wpb, int wt);
+
+}  // namespace vnp

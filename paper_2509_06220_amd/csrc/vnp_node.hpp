@@ -1,0 +1,86 @@
+// Device node primitives: the hypotenuse that combines two partial norms.
+//
+// Paper (Novakovic, arXiv 2509.06220), Sect. 1: a node needs no undue overflow or
+// underflow, monotonicity and a small relative error |eps_h| <= c eps.  Listing 2 meets
+// this with a division and a square root per node; Sect. 3 names the division as the
+// cost to remove.  The nodes here use no division:
+//
+//   hyp_d (binary64): let M be the larger of |a|, |b|, E its biased exponent clamped to
+//   [1, 2045] and k = 1023 - E.  With a' = a 2^k, b' = b 2^k (exact),
+//       hyp_d(a, b) = 2^-k * RN(sqrt(RN(a'^2 + RN(b'^2)))),
+//   i.e. one fma for the sum of squares and a correctly rounded square root, all in
+//   a range where nothing over- or underflows.  Relative error <= (1 + eps)^2 - 1.
+//   Inputs may carry a sign (leaves); a NaN input gives NaN, otherwise an infinite
+//   input gives +inf.  hyp_d(a, 0) = |a| exactly, since RN(sqrt(RN(a'^2))) = |a'| in
+//   binary floating point -- zero padding of the tree is therefore exact.
+//
+//   hyp_s (binary32): a^2 and b^2 are exact in binary64, so
+//       hyp_s(a, b) = RN_32(RN_64(sqrt(RN_64(a^2 + b^2)))),
+//   within (1 + 2^-28) eps_S of correctly rounded, with no scaling needed.
+//
+// The square root is the Goldschmidt/Newton sequence from v_rsq_f64 that the compiler
+// uses for a correctly rounded binary64 sqrt, minus its denormal rescaling: both nodes
+// only take square roots of 0, inf, NaN or values in [2^-300, 2^260], where rescaling
+// is never triggered, so the result is the correctly rounded sqrt.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vnp {
+
+// Correctly rounded sqrt for s in {+0, +inf, NaN} or [2^-767, 2^1023].
+__device__ __forceinline__ double sqrt_cr(double s)
+{
+    const double y = __builtin_amdgcn_rsq(s);
+    double g = s * y;
+    double h = y * 0.5;
+    const double r = __builtin_fma(-h, g, 0.5);
+    g = __builtin_fma(g, r, g);
+    h = __builtin_fma(h, r, h);
+    double d = __builtin_fma(-g, g, s);
+    g = __builtin_fma(d, h, g);
+    d = __builtin_fma(-g, g, s);
+    g = __builtin_fma(d, h, g);
+    // +0 and +inf are their own roots (class mask: +0 | -0 | +inf).
+    return __builtin_amdgcn_class(s, 0x260) ? s : g;
+}
+
+__device__ __forceinline__ uint32_t hi_word(double v) { return (uint32_t)(__double_as_longlong(v) >> 32); }
+
+// Node on non-negative partial norms (NaN / inf allowed).
+__device__ __forceinline__ double hyp_d(double a, double b)
+{
+    const uint32_t hm = max(hi_word(a), hi_word(b));
+    const int E = min(max((int)(hm >> 20), 1), 2045);
+    const int k = 1023 - E;
+    const double as = __builtin_amdgcn_ldexp(a, k);
+    const double bs = __builtin_amdgcn_ldexp(b, k);
+    const double s = __builtin_fma(as, as, bs * bs);
+    return __builtin_amdgcn_ldexp(sqrt_cr(s), -k);
+}
+
+// Node on raw elements (leaves): hyp_d(|a|, |b|).
+__device__ __forceinline__ double hyp_d_leaf(double a, double b)
+{
+    const uint32_t hm = max(hi_word(a) & 0x7fffffffu, hi_word(b) & 0x7fffffffu);
+    const int E = min(max((int)(hm >> 20), 1), 2045);
+    const int k = 1023 - E;
+    const double as = __builtin_amdgcn_ldexp(a, k);
+    const double bs = __builtin_amdgcn_ldexp(b, k);
+    const double s = __builtin_fma(as, as, bs * bs);
+    return __builtin_amdgcn_ldexp(sqrt_cr(s), -k);
+}
+
+__device__ __forceinline__ float hyp_s(float a, float b)
+{
+    const double A = (double)a, B = (double)b;
+    return (float)sqrt_cr(__builtin_fma(A, A, B * B));
+}
+
+__device__ __forceinline__ float hyp_s_leaf(float a, float b) { return hyp_s(a, b); }
+
+// |x| of a single leaf (a one-element subtree).
+__device__ __forceinline__ double leaf_abs(double v) { return __builtin_fabs(v); }
+__device__ __forceinline__ float leaf_abs(float v) { return __builtin_fabsf(v); }
+
+}  // namespace vnp

@@ -1,0 +1,249 @@
+// The canonical reduction tree and the device code that evaluates it.
+//
+// Paper (Novakovic, arXiv 2509.06220): any split of x into disjoint parts may be
+// combined by a hypotenuse node (Eq. (hr)); the vectorized algorithm Z keeps one
+// partial norm per vector lane, each reducing the elements in that lane by the
+// recursive tree, and reduces the lane vector at the end (Sect. 3, Listing 4 and the
+// lane example with p = 4, n = 16).  Results of such a vector algorithm are bitwise
+// reproducible for a fixed lane count (Sect. 3); OpenMP-style chunking keeps that
+// property only with a fixed reduction order (Sect. 3.1).
+//
+// The GPU tree fixes one lane layout and one reduction order for all launch shapes:
+//
+//   * elements are grouped in tiles of TILE = 64 lanes * VEC * ROWS consecutive logical
+//     indices (VEC = 2 for binary64, 4 for binary32: one 16-byte load per lane per row);
+//     within a tile, logical index i = row * (64 VEC) + lane * VEC + c;
+//   * the tree is the perfect binary tree over the zero-padded logical index whose
+//     levels consume index bits in this order: the ROWS bits (low to high; this is Z's
+//     per-lane recursion over rows), the c bits, the lane bits 0..5, then the tile index
+//     bits (low to high);
+//   * a node whose right operand is a padding zero returns its left operand exactly, so
+//     the result equals the same tree with absent children skipped.
+//
+// Any launch evaluates aligned power-of-two subtrees of this one tree (a wave: a tile or
+// a run of tiles; a block: a run of waves; the finish: the tree over block results), so
+// the value depends on the logical vector only.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vnp_node.hpp"
+
+namespace vnp {
+
+constexpr int WAVE = 64;
+constexpr int ROWS = 64;  // rows per tile: depth of the per-lane row tree is 6
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Vec;
+template <>
+struct Vec<double> {
+    using V = d2v;
+    static constexpr int N = 2;
+    __device__ static double get(const V &v, int c) { return v[c]; }
+    __device__ static V zero() { return V{0.0, 0.0}; }
+};
+template <>
+struct Vec<float> {
+    using V = f4v;
+    static constexpr int N = 4;
+    __device__ static float get(const V &v, int c) { return v[c]; }
+    __device__ static V zero() { return V{0.f, 0.f, 0.f, 0.f}; }
+};
+
+template <typename T>
+constexpr int64_t tile_elems() { return (int64_t)WAVE * Vec<T>::N * ROWS; }
+
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+
+// ---------------------------------------------------------------------------------
+// Loaders.  Row `r` of a tile, as seen by `lane`: the VEC consecutive logical elements
+// tile_base + r * (64 VEC) + lane * VEC + c.
+// ---------------------------------------------------------------------------------
+template <typename T>
+struct LoadFast {  // contiguous, 16-byte aligned, full tile
+    using V = typename Vec<T>::V;
+    const V *__restrict__ p;  // tile base
+    __device__ V operator()(int r, int lane) const { return __builtin_nontemporal_load(p + r * WAVE + lane); }
+};
+
+template <typename T>
+struct LoadGeneric {  // any stride / alignment / partial tile; zero beyond n
+    using V = typename Vec<T>::V;
+    const T *x;  // logical element i is x[i * inc]
+    int64_t inc, n, base;
+    __device__ V operator()(int r, int lane) const
+    {
+        V v = Vec<T>::zero();
+        const int64_t i0 = base + (int64_t)r * (WAVE * Vec<T>::N) + lane * Vec<T>::N;
+#pragma unroll
+        for (int c = 0; c < Vec<T>::N; ++c) {
+            const int64_t i = i0 + c;
+            v[c] = i < n ? x[i * inc] : T(0);
+        }
+        return v;
+    }
+};
+
+// ---------------------------------------------------------------------------------
+// Subtree roots in registers.
+// ---------------------------------------------------------------------------------
+
+// Butterfly over lane bits 0..5; the lower lane is always the left operand.  On return
+// every lane holds the root.
+template <class Node, typename T>
+__device__ __forceinline__ T lane_tree(const Node &nd, T t, int lane)
+{
+#pragma unroll
+    for (int s = 1; s < WAVE; s <<= 1) {
+        const T o = __shfl_xor(t, s);
+        const bool upper = (lane & s) != 0;
+        t = nd.node(upper ? o : t, upper ? t : o);
+    }
+    return t;
+}
+
+// Merge a new subtree root `cur` at level 0 of a binary-counter stack, given that `idx`
+// subtrees were pushed before (idx is wave-uniform).  After the push of the last of 2^L
+// subtrees, stk[L] holds the root of all of them.
+template <class Node, typename T, int L>
+__device__ __forceinline__ void push(const Node &nd, T (&stk)[L + 1], T cur, int idx)
+{
+    bool carry = true;
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const bool bit = (idx >> l) & 1;
+        if (carry && bit) cur = nd.node(stk[l], cur);
+        if (carry && !bit) stk[l] = cur;
+        carry = carry && bit;
+    }
+    if (carry) stk[L] = cur;
+}
+
+// Loads U rows (group g of tile t) into buf.
+template <typename T, int U, bool FAST>
+__device__ __forceinline__ void load_group(typename Vec<T>::V (&buf)[U], const T *x, int64_t n, int64_t inc,
+                                           int64_t t, int64_t ntiles, int g, int lane)
+{
+    using V = typename Vec<T>::V;
+    constexpr int64_t TE = tile_elems<T>();
+    const int64_t base = t * TE;
+    if (FAST && base + TE <= n) {
+        LoadFast<T> ld{reinterpret_cast<const V *>(x + base)};
+#pragma unroll
+        for (int u = 0; u < U; ++u) buf[u] = ld(g * U + u, lane);
+    } else if (t < ntiles) {
+        LoadGeneric<T> ld{x, inc, n, base};
+#pragma unroll
+        for (int u = 0; u < U; ++u) buf[u] = ld(g * U + u, lane);
+    } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u) buf[u] = Vec<T>::zero();
+    }
+}
+
+// Root of WT consecutive tiles starting at tile index t0 (tiles at or beyond ntiles are
+// padding): per-lane row trees (rows in groups of U), then columns, then lanes, for each
+// tile; then the tiles.  One group of rows is always in flight while the previous one is
+// reduced.  FAST: contiguous 16-byte-aligned input (full tiles use vector loads).
+template <class Node, int U, int WT, bool FAST>
+__device__ __forceinline__ typename Node::T wave_root(const Node &nd, const typename Node::T *x, int64_t n,
+                                                      int64_t inc, int64_t t0, int64_t ntiles, int lane)
+{
+    using T = typename Node::T;
+    using VV = Vec<T>;
+    using V = typename VV::V;
+    constexpr int C = VV::N;
+    constexpr int G = ROWS / U;
+    constexpr int LG = ilog2(G);
+    constexpr int LW = ilog2(WT);
+    constexpr int Q = WT * G;
+    static_assert(U >= 2 && (U & (U - 1)) == 0 && G >= 2, "U must be a power of two in [2, ROWS/2]");
+
+    T rstk[C][LG + 1];
+    T tstk[LW + 1];
+
+    auto step = [&](const V(&v)[U], int q) {
+        const int g = q % G;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            T w[U / 2];
+#pragma unroll
+            for (int u = 0; u < U / 2; ++u) w[u] = nd.leaf(VV::get(v[2 * u], c), VV::get(v[2 * u + 1], c));
+#pragma unroll
+            for (int s = U / 4; s >= 1; s >>= 1) {
+#pragma unroll
+                for (int u = 0; u < s; ++u) w[u] = nd.node(w[2 * u], w[2 * u + 1]);
+            }
+            push<Node, T, LG>(nd, rstk[c], w[0], g);
+        }
+        if (g == G - 1) {
+            T t;
+            if constexpr (C == 2) {
+                t = nd.node(rstk[0][LG], rstk[1][LG]);
+            } else {
+                t = nd.node(nd.node(rstk[0][LG], rstk[1][LG]), nd.node(rstk[2][LG], rstk[3][LG]));
+            }
+            t = lane_tree(nd, t, lane);
+            push<Node, T, LW>(nd, tstk, t, q / G);
+        }
+    };
+
+    V a[U], b[U];
+    load_group<T, U, FAST>(a, x, n, inc, t0, ntiles, 0, lane);
+#pragma unroll 1
+    for (int q = 0; q < Q; q += 2) {
+        load_group<T, U, FAST>(b, x, n, inc, t0 + (q + 1) / G, ntiles, (q + 1) % G, lane);
+        step(a, q);
+        if (q + 2 < Q) load_group<T, U, FAST>(a, x, n, inc, t0 + (q + 2) / G, ntiles, (q + 2) % G, lane);
+        step(b, q + 1);
+    }
+    return tstk[LW];
+}
+
+// Tree over v[0..m) (m a power of two) held in LDS, pairs at growing strides; the root
+// ends in v[0].  Call with the whole block; contains barriers.
+template <class Node, typename T>
+__device__ __forceinline__ void lds_tree(const Node &nd, T *v, int m)
+{
+    for (int s = 1; s < m; s <<= 1) {
+        __syncthreads();
+        for (int i = threadIdx.x * 2 * s; i < m; i += blockDim.x * 2 * s) v[i] = nd.node(v[i], v[i + s]);
+    }
+    __syncthreads();
+}
+
+// Fixed tree over r[0..count) (zero-padded to a power of two), by the whole block.
+// r is overwritten (chunk roots are compacted to the front between passes).  The root is
+// returned to every thread.  sbuf: LDS of blockDim.x elements.
+template <class Node, typename T>
+__device__ T block_finish(const Node &nd, T *r, int64_t count, T *sbuf)
+{
+    const int nt = blockDim.x;
+    const int64_t chunk = (int64_t)nt * 8;
+    while (count > 1) {
+        const int64_t nchunks = (count + chunk - 1) / chunk;
+        for (int64_t ck = 0; ck < nchunks; ++ck) {
+            const int64_t b0 = ck * chunk + (int64_t)threadIdx.x * 8;
+            T e[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) e[j] = (b0 + j < count) ? r[b0 + j] : T(0);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) e[j] = nd.node(e[2 * j], e[2 * j + 1]);
+            e[0] = nd.node(e[0], e[1]);
+            e[2] = nd.node(e[2], e[3]);
+            sbuf[threadIdx.x] = nd.node(e[0], e[2]);
+            lds_tree(nd, sbuf, nt);
+            if (threadIdx.x == 0) r[ck] = sbuf[0];
+            __syncthreads();
+        }
+        count = nchunks;
+    }
+    __syncthreads();
+    return r[0];
+}
+
+}  // namespace vnp
