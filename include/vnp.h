@@ -130,7 +130,8 @@ int64_t vnp_tile_elems(int dtype);
 int vnp_finalize(void);
 
 /* Launch-shape override for tests and tuning: waves per block and tiles per wave
- * (powers of two; 0 = automatic).  Results never depend on it.  Process-wide. */
+ * (powers of two, at most 16 and 2^12; 0 = automatic).  Results never depend on it.
+ * Process-wide. */
 int vnp_set_launch_shape(int waves_per_block, int tiles_per_wave);
 
 #ifdef __cplusplus

@@ -15,12 +15,12 @@
 //   binary floating point -- zero padding of the tree is therefore exact.
 //
 //   hyp_s (binary32): a^2 and b^2 are exact in binary64, so
-//       hyp_s(a, b) = RN_32(RN_64(sqrt(RN_64(a^2 + b^2)))),
-//   within (1 + 2^-28) eps_S of correctly rounded, with no scaling needed.
+//       hyp_s(a, b) = RN_32(sqrt(RN_64(a^2 + b^2)) (1 + d)),  |d| < 2^-43,
+//   with relative error below (1 + 2^-18) eps_S and no scaling needed.
 //
 // The square root is the Goldschmidt/Newton sequence from v_rsq_f64 that the compiler
-// uses for a correctly rounded binary64 sqrt, minus its denormal rescaling: both nodes
-// only take square roots of 0, inf, NaN or values in [2^-300, 2^260], where rescaling
+// uses for a correctly rounded binary64 sqrt, minus its denormal rescaling: the nodes
+// only take square roots of 0, inf, NaN or values in [2^-760, 2^1002], where rescaling
 // is never triggered, so the result is the correctly rounded sqrt.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -28,8 +28,8 @@
 
 namespace vnp {
 
-// Correctly rounded sqrt for s in {+0, +inf, NaN} or [2^-767, 2^1023].
-__device__ __forceinline__ double sqrt_cr(double s)
+// Correctly rounded sqrt for s in [2^-767, 2^1023] (no special values).
+__device__ __forceinline__ double sqrt_core(double s)
 {
     const double y = __builtin_amdgcn_rsq(s);
     double g = s * y;
@@ -40,27 +40,21 @@ __device__ __forceinline__ double sqrt_cr(double s)
     double d = __builtin_fma(-g, g, s);
     g = __builtin_fma(d, h, g);
     d = __builtin_fma(-g, g, s);
-    g = __builtin_fma(d, h, g);
+    return __builtin_fma(d, h, g);
+}
+
+// Correctly rounded sqrt for s in {+0, +inf, NaN} or [2^-767, 2^1023].
+__device__ __forceinline__ double sqrt_cr(double s)
+{
+    const double g = sqrt_core(s);
     // +0 and +inf are their own roots (class mask: +0 | -0 | +inf).
     return __builtin_amdgcn_class(s, 0x260) ? s : g;
 }
 
 __device__ __forceinline__ uint32_t hi_word(double v) { return (uint32_t)(__double_as_longlong(v) >> 32); }
 
-// Node on non-negative partial norms (NaN / inf allowed).
-__device__ __forceinline__ double hyp_d(double a, double b)
-{
-    const uint32_t hm = max(hi_word(a), hi_word(b));
-    const int E = min(max((int)(hm >> 20), 1), 2045);
-    const int k = 1023 - E;
-    const double as = __builtin_amdgcn_ldexp(a, k);
-    const double bs = __builtin_amdgcn_ldexp(b, k);
-    const double s = __builtin_fma(as, as, bs * bs);
-    return __builtin_amdgcn_ldexp(sqrt_cr(s), -k);
-}
-
-// Node on raw elements (leaves): hyp_d(|a|, |b|).
-__device__ __forceinline__ double hyp_d_leaf(double a, double b)
+// Exponent-scaled evaluation, valid for all inputs (signs allowed).
+__device__ __forceinline__ double hyp_d_scaled(double a, double b)
 {
     const uint32_t hm = max(hi_word(a) & 0x7fffffffu, hi_word(b) & 0x7fffffffu);
     const int E = min(max((int)(hm >> 20), 1), 2045);
@@ -71,10 +65,44 @@ __device__ __forceinline__ double hyp_d_leaf(double a, double b)
     return __builtin_amdgcn_ldexp(sqrt_cr(s), -k);
 }
 
+// The binary64 node is defined piecewise.  When the larger operand lies in
+// [2^-380, 2^500), RN(a^2 + RN(b^2)) neither overflows nor underflows and its square
+// root is in the range where sqrt_core is exact, so the node is
+// RN(sqrt(RN(a^2 + RN(b^2)))) computed directly; elsewhere (zeros, tiny or huge
+// operands, inf, NaN) it is the scaled form above, evaluated only for the lanes that
+// need it.  Both forms have relative error at most (1 + eps)^2 - 1 and give
+// node(a, 0) = |a|; they differ only where b^2 underflows in one form and not in the
+// other while a^2 is exactly half-way between two doubles.
+__device__ __forceinline__ double hyp_d(double a, double b)
+{
+    const uint32_t hm = max(hi_word(a) & 0x7fffffffu, hi_word(b) & 0x7fffffffu);
+    // exponent field of the larger operand in [1023 - 380, 1023 + 500)
+    const bool fast = (hm - 0x28300000u) < (0x5F300000u - 0x28300000u);
+    double r = sqrt_core(__builtin_fma(a, a, b * b));
+    if (!fast) r = hyp_d_scaled(a, b);
+    return r;
+}
+
+__device__ __forceinline__ double hyp_d_leaf(double a, double b) { return hyp_d(a, b); }
+
+// sqrt(s) to about 2^-44 relative (one Goldschmidt step from v_rsq_f64), for s in
+// [2^-767, 2^1023]; +0, +inf and NaN map to themselves.  Rounded to binary32 this is the
+// correctly rounded single-precision root except within 2^-19 ulp of a rounding
+// boundary.
+__device__ __forceinline__ double sqrt_for_f32(double s)
+{
+    const double y = __builtin_amdgcn_rsq(s);
+    const double g = s * y;
+    const double h = y * 0.5;
+    const double r = __builtin_fma(-h, g, 0.5);
+    const double g1 = __builtin_fma(g, r, g);
+    return __builtin_amdgcn_class(s, 0x260) ? s : g1;
+}
+
 __device__ __forceinline__ float hyp_s(float a, float b)
 {
     const double A = (double)a, B = (double)b;
-    return (float)sqrt_cr(__builtin_fma(A, A, B * B));
+    return (float)sqrt_for_f32(__builtin_fma(A, A, B * B));
 }
 
 __device__ __forceinline__ float hyp_s_leaf(float a, float b) { return hyp_s(a, b); }

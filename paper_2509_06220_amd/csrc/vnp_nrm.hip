@@ -19,23 +19,44 @@
 
 namespace vnp {
 
+// Rows per load group (one group is in flight per wave while the previous one is
+// reduced): 8 KiB per wave for the binary64 hypot node, 4 KiB where the node is heavier
+// in registers or arithmetic (measured on MI355X; results never depend on it).
+template <class Node>
+struct RowsInFlight {
+    static constexpr int value = 4;
+};
+template <>
+struct RowsInFlight<HypNode<double>> {
+    static constexpr int value = 8;
+};
+template <>
+struct RowsInFlight<SumNode<double>> {
+    static constexpr int value = 8;
+};
+template <>
+struct RowsInFlight<MaxNode<double>> {
+    static constexpr int value = 8;
+};
+
 // ---------------------------------------------------------------------------------
 // Kernel
 // ---------------------------------------------------------------------------------
-template <class Node, int U, int WT, bool FAST>
+template <class Node, int U, bool FAST>
 __global__ void __launch_bounds__(1024)
-    nrm_kernel(Node nd, const typename Node::T *x, int64_t n, int64_t inc, int64_t ntiles,
+    nrm_kernel(Node nd, const typename Node::T *x, int64_t n, int64_t inc, int64_t ntiles, int lwt,
                typename Node::T *roots, unsigned int *ticket, typename Node::T *res)
 {
     using T = typename Node::T;
     __shared__ T sbuf[1024];
     __shared__ unsigned int s_last;
     const int lane = threadIdx.x & (WAVE - 1);
-    const int wave = threadIdx.x / WAVE;
+    // wave index: uniform within the wave (tell the compiler, so the loops stay scalar)
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int wpb = blockDim.x / WAVE;
-    const int64_t t0 = ((int64_t)blockIdx.x * wpb + wave) * WT;
+    const int64_t t0 = ((int64_t)blockIdx.x * wpb + wave) << lwt;
 
-    const T r = wave_root<Node, U, WT, FAST>(nd, x, n, inc, t0, ntiles, lane);
+    const T r = wave_root<Node, U, FAST>(nd, x, n, inc, t0, ntiles, lwt, lane);
     if (lane == 0) sbuf[wave] = r;
     lds_tree(nd, sbuf, wpb);
     if (gridDim.x == 1) {
@@ -65,36 +86,42 @@ __global__ void write_zero_kernel(T *res)
 // ---------------------------------------------------------------------------------
 // Launch configuration
 // ---------------------------------------------------------------------------------
-static int g_force_wpb = 0, g_force_wt = 0;
+static int g_force_wpb = 0, g_force_lwt = -1;
 
 struct Shape {
-    int wpb, wt;
+    int wpb, lwt;  // waves per block, log2(tiles per wave)
 };
 
+static int cu_count()
+{
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            cus = v;
+        else
+            cus = 256;
+    }
+    return cus;
+}
+
+// Persistent-style shape: blocks of 8 waves, about 32 waves per compute unit in total
+// (two rounds of resident blocks), each wave streaming an aligned run of 2^lwt tiles (a
+// run's root is a subtree of the canonical tree, so the shape never changes the result).
 static Shape choose_shape(int64_t ntiles)
 {
-    Shape s;
-    if (g_force_wpb > 0 || g_force_wt > 0) {
-        s.wpb = g_force_wpb > 0 ? g_force_wpb : 4;
-        s.wt = g_force_wt > 0 ? g_force_wt : 1;
-    } else if (ntiles >= (int64_t)1 << 16) {
-        s = {4, 4};
-    } else if (ntiles >= (int64_t)1 << 13) {
-        s = {4, 2};
-    } else if (ntiles >= 1024) {
-        s = {4, 1};
-    } else {
-        s = {2, 1};
-    }
-    // keep the number of block roots within what the finish handles comfortably
-    while ((ntiles + (int64_t)s.wpb * s.wt - 1) / ((int64_t)s.wpb * s.wt) > ((int64_t)1 << 20)) {
-        if (s.wt < 8)
-            s.wt *= 2;
-        else if (s.wpb < 16)
-            s.wpb *= 2;
-        else
-            break;
-    }
+    const int64_t target_waves = (int64_t)cu_count() * 32;
+    Shape s{8, 0};
+    while (((int64_t)1 << s.lwt) * target_waves < ntiles && s.lwt < MAX_LWT) ++s.lwt;
+    if (ntiles < (int64_t)cu_count() * 32) s.wpb = 4;
+    if (ntiles < (int64_t)cu_count() * 4) s.wpb = 1;
+    if (g_force_wpb > 0) s.wpb = g_force_wpb;
+    if (g_force_lwt >= 0) s.lwt = g_force_lwt;
+    // keep the number of block roots within what one block finishes quickly
+    while ((ntiles + ((int64_t)s.wpb << s.lwt) - 1) / ((int64_t)s.wpb << s.lwt) > ((int64_t)1 << 20) &&
+           s.lwt < MAX_LWT)
+        ++s.lwt;
     return s;
 }
 
@@ -161,17 +188,17 @@ int release_workspaces()
 // ---------------------------------------------------------------------------------
 // Dispatch
 // ---------------------------------------------------------------------------------
-template <class Node, int U, int WT>
-static void launch_wt(const Node &nd, bool fast, dim3 grid, dim3 block, hipStream_t st, const typename Node::T *x,
-                      int64_t n, int64_t inc, int64_t ntiles, typename Node::T *roots, unsigned *ticket,
-                      typename Node::T *res)
+template <class Node>
+static void launch(const Node &nd, bool fast, dim3 grid, dim3 block, hipStream_t st, const typename Node::T *x,
+                   int64_t n, int64_t inc, int64_t ntiles, int lwt, typename Node::T *roots, unsigned *ticket,
+                   typename Node::T *res)
 {
     if (fast)
-        hipLaunchKernelGGL((nrm_kernel<Node, U, WT, true>), grid, block, 0, st, nd, x, n, inc, ntiles, roots, ticket,
-                           res);
+        hipLaunchKernelGGL((nrm_kernel<Node, RowsInFlight<Node>::value, true>), grid, block, 0, st, nd, x, n, inc, ntiles, lwt, roots,
+                           ticket, res);
     else
-        hipLaunchKernelGGL((nrm_kernel<Node, U, WT, false>), grid, block, 0, st, nd, x, n, inc, ntiles, roots, ticket,
-                           res);
+        hipLaunchKernelGGL((nrm_kernel<Node, RowsInFlight<Node>::value, false>), grid, block, 0, st, nd, x, n, inc, ntiles, lwt, roots,
+                           ticket, res);
 }
 
 template <class Node>
@@ -187,31 +214,25 @@ static int run_norm(const Node &nd, int64_t n, const typename Node::T *x, int64_
     constexpr int64_t TE = tile_elems<T>();
     const int64_t ntiles = (n + TE - 1) / TE;
     const Shape s = choose_shape(ntiles);
-    const int64_t per_block = (int64_t)s.wpb * s.wt;
+    const int64_t per_block = (int64_t)s.wpb << s.lwt;
     const int64_t nblocks = (ntiles + per_block - 1) / per_block;
     Workspace *ws = nullptr;
     int rc = get_workspace(stream, sizeof(T) * (size_t)nblocks, &ws);
     if (rc) return rc;
     const T *base = incx >= 0 ? x : x + (n - 1) * (-incx);
     const bool fast = incx == 1 && ((uintptr_t)x & 15) == 0;
-    const dim3 grid((unsigned)nblocks), block((unsigned)(s.wpb * WAVE));
-    T *roots = static_cast<T *>(ws->roots);
-    switch (s.wt) {
-    case 1: launch_wt<Node, 4, 1>(nd, fast, grid, block, st, base, n, incx, ntiles, roots, ws->ticket, res); break;
-    case 2: launch_wt<Node, 4, 2>(nd, fast, grid, block, st, base, n, incx, ntiles, roots, ws->ticket, res); break;
-    case 4: launch_wt<Node, 4, 4>(nd, fast, grid, block, st, base, n, incx, ntiles, roots, ws->ticket, res); break;
-    default: launch_wt<Node, 4, 8>(nd, fast, grid, block, st, base, n, incx, ntiles, roots, ws->ticket, res); break;
-    }
+    launch(nd, fast, dim3((unsigned)nblocks), dim3((unsigned)(s.wpb * WAVE)), st, base, n, incx, ntiles, s.lwt,
+           static_cast<T *>(ws->roots), ws->ticket, res);
     return (int)hipGetLastError();
 }
 
 int set_launch_shape(int wpb, int wt)
 {
-    auto pow2 = [](int v) { return v == 0 || (v > 0 && (v & (v - 1)) == 0); };
-    if (!pow2(wpb) || wpb > 16) return -1;
-    if (!pow2(wt) || wt > 8) return -2;
+    auto pow2 = [](int v) { return v > 0 && (v & (v - 1)) == 0; };
+    if (wpb != 0 && (!pow2(wpb) || wpb > 16)) return -1;
+    if (wt != 0 && (!pow2(wt) || wt > (1 << MAX_LWT))) return -2;
     g_force_wpb = wpb;
-    g_force_wt = wt;
+    g_force_lwt = wt == 0 ? -1 : ilog2(wt);
     return 0;
 }
 

@@ -123,35 +123,33 @@ __device__ __forceinline__ void push(const Node &nd, T (&stk)[L + 1], T cur, int
     if (carry) stk[L] = cur;
 }
 
-// Loads U rows (group g of tile t) into buf.
-template <typename T, int U, bool FAST>
-__device__ __forceinline__ void load_group(typename Vec<T>::V (&buf)[U], const T *x, int64_t n, int64_t inc,
-                                           int64_t t, int64_t ntiles, int g, int lane)
+// Loads U rows (group g of a tile) into buf.
+template <int U, class Load>
+__device__ __forceinline__ void load_rows(typename Load::V (&buf)[U], const Load &ld, int g, int lane)
 {
-    using V = typename Vec<T>::V;
-    constexpr int64_t TE = tile_elems<T>();
-    const int64_t base = t * TE;
-    if (FAST && base + TE <= n) {
-        LoadFast<T> ld{reinterpret_cast<const V *>(x + base)};
 #pragma unroll
-        for (int u = 0; u < U; ++u) buf[u] = ld(g * U + u, lane);
-    } else if (t < ntiles) {
-        LoadGeneric<T> ld{x, inc, n, base};
-#pragma unroll
-        for (int u = 0; u < U; ++u) buf[u] = ld(g * U + u, lane);
-    } else {
-#pragma unroll
-        for (int u = 0; u < U; ++u) buf[u] = Vec<T>::zero();
-    }
+    for (int u = 0; u < U; ++u) buf[u] = ld(g * U + u, lane);
 }
 
-// Root of WT consecutive tiles starting at tile index t0 (tiles at or beyond ntiles are
-// padding): per-lane row trees (rows in groups of U), then columns, then lanes, for each
-// tile; then the tiles.  One group of rows is always in flight while the previous one is
-// reduced.  FAST: contiguous 16-byte-aligned input (full tiles use vector loads).
-template <class Node, int U, int WT, bool FAST>
-__device__ __forceinline__ typename Node::T wave_root(const Node &nd, const typename Node::T *x, int64_t n,
-                                                      int64_t inc, int64_t t0, int64_t ntiles, int lane)
+// A wave-uniform copy of v (all lanes hold the same value): lets the compiler keep it in
+// scalar registers.
+__device__ __forceinline__ double uniform(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float uniform(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// Root of one tile through the generic loader (used for the partial tail tile of a
+// contiguous input, kept out of line so the vector-load loop keeps its registers).
+template <class Node, int U>
+__device__ __noinline__ typename Node::T generic_tile_root(Node nd, const typename Node::T *x, int64_t n, int64_t inc,
+                                                           int64_t t, int lane)
 {
     using T = typename Node::T;
     using VV = Vec<T>;
@@ -159,15 +157,76 @@ __device__ __forceinline__ typename Node::T wave_root(const Node &nd, const type
     constexpr int C = VV::N;
     constexpr int G = ROWS / U;
     constexpr int LG = ilog2(G);
-    constexpr int LW = ilog2(WT);
-    constexpr int Q = WT * G;
+    const LoadGeneric<T> ld{x, inc, n, t * tile_elems<T>()};
+    T rstk[C][LG + 1];
+#pragma unroll 1
+    for (int g = 0; g < G; ++g) {
+        V v[U];
+        load_rows<U>(v, ld, g, lane);
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            T w[U / 2];
+#pragma unroll
+            for (int u = 0; u < U / 2; ++u) w[u] = nd.leaf(VV::get(v[2 * u], c), VV::get(v[2 * u + 1], c));
+#pragma unroll
+            for (int s = U / 4; s >= 1; s >>= 1) {
+#pragma unroll
+                for (int u = 0; u < s; ++u) w[u] = nd.node(w[2 * u], w[2 * u + 1]);
+            }
+            push<Node, T, LG>(nd, rstk[c], w[0], g);
+        }
+    }
+    T r;
+    if constexpr (C == 2) {
+        r = nd.node(rstk[0][LG], rstk[1][LG]);
+    } else {
+        r = nd.node(nd.node(rstk[0][LG], rstk[1][LG]), nd.node(rstk[2][LG], rstk[3][LG]));
+    }
+    return lane_tree(nd, r, lane);
+}
+
+constexpr int MAX_LWT = 12;  // a wave covers at most 2^12 tiles
+
+// Root of the 2^lwt consecutive tiles starting at tile index t0 (tiles at or beyond
+// ntiles are padding and are skipped exactly): per-lane row trees (rows in groups of U),
+// then columns, then lanes, for each tile; then the tiles, by a binary-counter stack of
+// tile roots.  One group of rows is always in flight while the previous one is reduced,
+// across tile boundaries.  FAST: contiguous 16-byte-aligned input.
+template <class Node, int U, bool FAST>
+__device__ __forceinline__ typename Node::T wave_root(const Node &nd, const typename Node::T *x, int64_t n,
+                                                      int64_t inc, int64_t t0, int64_t ntiles, int lwt, int lane)
+{
+    using T = typename Node::T;
+    using VV = Vec<T>;
+    using V = typename VV::V;
+    constexpr int C = VV::N;
+    constexpr int G = ROWS / U;
+    constexpr int LG = ilog2(G);
+    constexpr int64_t TE = tile_elems<T>();
     static_assert(U >= 2 && (U & (U - 1)) == 0 && G >= 2, "U must be a power of two in [2, ROWS/2]");
 
+    if (t0 >= ntiles) return T(0);
+    const int64_t left = ntiles - t0;
+    const int ktiles = left < ((int64_t)1 << lwt) ? (int)left : (1 << lwt);
+    const int Q = ktiles * G;  // row groups to reduce (even)
+
     T rstk[C][LG + 1];
-    T tstk[LW + 1];
+    T tstk[MAX_LWT + 1];
+
+    // binary counter over tile roots; entries stay wave-uniform
+    auto push_tile = [&](T t, int idx) {
+        bool carry = true;
+#pragma unroll
+        for (int l = 0; l < MAX_LWT; ++l) {
+            const bool bit = (idx >> l) & 1;
+            if (carry && bit) t = uniform(nd.node(tstk[l], t));
+            if (carry && !bit) tstk[l] = t;
+            carry = carry && bit;
+        }
+    };
 
     auto step = [&](const V(&v)[U], int q) {
-        const int g = q % G;
+        const int g = q & (G - 1);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             T w[U / 2];
@@ -187,21 +246,62 @@ __device__ __forceinline__ typename Node::T wave_root(const Node &nd, const type
             } else {
                 t = nd.node(nd.node(rstk[0][LG], rstk[1][LG]), nd.node(rstk[2][LG], rstk[3][LG]));
             }
-            t = lane_tree(nd, t, lane);
-            push<Node, T, LW>(nd, tstk, t, q / G);
+            push_tile(uniform(lane_tree(nd, t, lane)), q >> LG);
         }
     };
 
-    V a[U], b[U];
-    load_group<T, U, FAST>(a, x, n, inc, t0, ntiles, 0, lane);
+    // Stream row groups [q0, q1) of the run through `ld_of(tile)`, one group in flight.
+    // Full tiles of contiguous aligned input use vector loads only, so the loop waits
+    // for exactly the previous group; the one partial tail tile goes through the
+    // generic loader in a loop of its own.
+    auto stream_groups = [&](auto ld_of, int q0, int q1) {
+        // q1 - q0 is even.  In the steady-state loop every prefetch is unconditional, so
+        // the wait before reducing a buffer covers exactly that buffer's loads; the
+        // scheduling barriers keep each group's reduction between its successor's loads
+        // and its own wait.
+        V a[U], b[U];
+        load_rows<U>(a, ld_of(t0 + (q0 >> LG)), q0 & (G - 1), lane);
+        int q = q0;
 #pragma unroll 1
-    for (int q = 0; q < Q; q += 2) {
-        load_group<T, U, FAST>(b, x, n, inc, t0 + (q + 1) / G, ntiles, (q + 1) % G, lane);
+        for (; q + 2 < q1; q += 2) {
+            load_rows<U>(b, ld_of(t0 + ((q + 1) >> LG)), (q + 1) & (G - 1), lane);
+            __builtin_amdgcn_sched_barrier(0);
+            step(a, q);
+            __builtin_amdgcn_sched_barrier(0);
+            load_rows<U>(a, ld_of(t0 + ((q + 2) >> LG)), (q + 2) & (G - 1), lane);
+            __builtin_amdgcn_sched_barrier(0);
+            step(b, q + 1);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        load_rows<U>(b, ld_of(t0 + ((q + 1) >> LG)), (q + 1) & (G - 1), lane);
+        __builtin_amdgcn_sched_barrier(0);
         step(a, q);
-        if (q + 2 < Q) load_group<T, U, FAST>(a, x, n, inc, t0 + (q + 2) / G, ntiles, (q + 2) % G, lane);
+        __builtin_amdgcn_sched_barrier(0);
         step(b, q + 1);
+    };
+    using TV = typename VV::V;
+    auto generic = [&](int64_t t) { return LoadGeneric<T>{x, inc, n, t * TE}; };
+    if constexpr (FAST) {
+        const int64_t full = n / TE;  // tiles entirely inside [0, n)
+        const int kfull = full <= t0 ? 0 : (full - t0 < ktiles ? (int)(full - t0) : ktiles);
+        auto fast = [&](int64_t t) { return LoadFast<T>{reinterpret_cast<const TV *>(x + t * TE)}; };
+        if (kfull > 0) stream_groups(fast, 0, kfull * G);
+        if (kfull < ktiles) push_tile(uniform(generic_tile_root<Node, U>(nd, x, n, inc, t0 + kfull, lane)), kfull);
+    } else {
+        stream_groups(generic, 0, Q);
     }
-    return tstk[LW];
+    // Root of the zero-padded run of 2^lwt tiles: ktiles were pushed; a missing right
+    // subtree is zero and node(a, 0) = a, so only the filled levels combine.
+    T cur = T(0);
+    bool any = false;
+#pragma unroll
+    for (int l = 0; l < MAX_LWT; ++l) {
+        if (l < lwt + 1 && ((ktiles >> l) & 1)) {
+            cur = any ? uniform(nd.node(tstk[l], cur)) : tstk[l];
+            any = true;
+        }
+    }
+    return cur;
 }
 
 // Tree over v[0..m) (m a power of two) held in LDS, pairs at growing strides; the root
