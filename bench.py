@@ -49,12 +49,16 @@ def traffic_per_launch():
     return t.get("bytes_per_launch")
 
 
-def time_steps(fn, steps, warmup, stream):
+def time_steps(fn, steps, warmup, stream, min_warm_s=0.5):
     import torch
 
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < min_warm_s:  # let clocks settle (untimed)
+        fn()
+        torch.cuda.synchronize()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t0 = time.perf_counter()
     for a, b in ev:
@@ -116,7 +120,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--cpu-sample-log2", type=int, default=24)
+    ap.add_argument("--cpu-sample-log2", type=int, default=30)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 2 GiB device copy 5 times (scale of the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (the multi-GPU sharding "
@@ -127,6 +133,17 @@ def main():
 
     import paper_2509_06220_amd as vnp
     import vnp_gen
+
+    if args.copy_calibration:
+        nb = 1 << 31
+        src = torch.empty(nb // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        vnp_gen.dev_fill(src, kind="u11")
+        for _ in range(5):
+            vnp_gen.dev_copy(dst.data_ptr(), src.data_ptr(), nb, 0, torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nb, "launches": 5}), flush=True)
+        return
 
     n = 1 << 30
     x = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -143,8 +160,8 @@ def main():
     achieved = nbytes / (kern_ms / 1e3) / 1e9
     tr = traffic_per_launch()
     # empirical ceiling: a plain streaming read of the same buffer
-    ceil_out = torch.empty(8192, dtype=torch.int32, device="cuda")
-    _, per_read = time_steps(lambda: vnp_gen.dev_read(x.data_ptr(), nbytes, ceil_out.data_ptr(), 8192,
+    ceil_out = torch.empty(16384, dtype=torch.int32, device="cuda")
+    _, per_read = time_steps(lambda: vnp_gen.dev_read(x.data_ptr(), nbytes, ceil_out.data_ptr(), 16384,
                                                       stream.cuda_stream), 10, 2, stream)
     read_gbs = nbytes / (statistics.mean(per_read) / 1e3) / 1e9
     line = {

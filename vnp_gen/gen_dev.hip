@@ -87,20 +87,26 @@ __global__ void copy_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ d
         dst[i] = src[i];
 }
 
-// Streaming read of nvec 16-byte vectors; xor-folds them so the loads are live and
+// Streaming read of nvec 16-byte vectors: block b reads one contiguous chunk with
+// non-temporal loads, 8 in flight per thread; xor-folds them so the loads are live and
 // writes one word per block.
-__global__ void __launch_bounds__(256) read_kernel(const uint4 *__restrict__ src, int64_t nvec, uint32_t *out)
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) read_kernel(const u4v *__restrict__ src, int64_t nvec, uint32_t *out)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t per = (nvec + gridDim.x - 1) / gridDim.x;
+    const int64_t b0 = (int64_t)blockIdx.x * per;
+    const int64_t b1 = b0 + per < nvec ? b0 + per : nvec;
     uint32_t acc = 0;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i + 3 * stride < nvec; i += 4 * stride) {
-        const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
-        acc ^= a.x ^ a.y ^ a.z ^ a.w ^ b.x ^ b.y ^ b.z ^ b.w ^ c.x ^ c.y ^ c.z ^ c.w ^ d.x ^ d.y ^ d.z ^ d.w;
-    }
-    for (; i < nvec; i += stride) {
-        const uint4 a = src[i];
-        acc ^= a.x ^ a.y ^ a.z ^ a.w;
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += 256 * 8) {
+        u4v v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t j = i + u * 256;
+            v[u] = j < b1 ? __builtin_nontemporal_load(src + j) : u4v{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
     }
     __shared__ uint32_t red[256];
     red[threadIdx.x] = acc;
@@ -153,7 +159,7 @@ int vnpg_dev_copy(void *dst, const void *src, int64_t bytes, int blocks, void *h
 int vnpg_dev_read(const void *src, int64_t bytes, uint32_t *out, int blocks, void *hstream)
 {
     if (bytes <= 0 || (bytes & 15) || (((uintptr_t)src) & 15) || blocks <= 0) return -1;
-    hipLaunchKernelGGL(read_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)hstream, (const uint4 *)src,
+    hipLaunchKernelGGL(read_kernel, dim3(blocks), dim3(256), 0, (hipStream_t)hstream, (const u4v *)src,
                        bytes / 16, out);
     return (int)hipGetLastError();
 }
