@@ -75,46 +75,60 @@ int vnp_snrmp(int64_t n, const float *x, int64_t incx, float p, float *res, void
 
 /* ------------------------------------------------------------------------------------
  * Batched segments in one launch.  Paper: norms of the columns of a multi-dimensional
- * array, then combined (Sect. 3.1).  Segment s is x[offsets[s] .. offsets[s+1]) (device
- * int64 array of nseg + 1 non-decreasing entries, offsets[0] >= 0); its norm goes to
- * res[s].  Each segment's result is bitwise equal to the single-vector call on it.
- * Errors: nseg < 0 -> -1; offsets == NULL -> -2; x == NULL -> -3; res == NULL -> -4
- * (dnrmp_batched: p invalid -> -4, res == NULL -> -5).  Offsets are not validated on
- * the device beyond clamping lengths at 0; out-of-range offsets are undefined behaviour.
+ * array, computed independently (Sect. 3.1).  x holds n_total elements; segment s is
+ * x[offsets[s] .. offsets[s+1]) (offsets: device int64 array of nseg + 1 entries; a
+ * negative length counts as empty) and its norm goes to res[s].  Each segment's result is
+ * bitwise equal to the single-vector call on it.  Segments are processed in one
+ * persistent launch (plus a one-block setup launch) with a per-stream workspace.
+ * Errors: nseg < 0 -> -1; offsets == NULL -> -2; n_total < 0 or > VNP_MAX_N -> -3;
+ * x == NULL -> -4; res == NULL -> -5 (p-norm: p <= 0 or NaN -> -5, res == NULL -> -6).
+ * A segment reaching outside [0, n_total) is detected on the device: then every res[s]
+ * is NaN and no data is read.
  * ---------------------------------------------------------------------------------- */
-int vnp_dnrmf_batched(int64_t nseg, const int64_t *offsets, const double *x, double *res, void *stream);
-int vnp_snrmf_batched(int64_t nseg, const int64_t *offsets, const float *x, float *res, void *stream);
-int vnp_dnrmp_batched(int64_t nseg, const int64_t *offsets, const double *x, double p, double *res, void *stream);
-int vnp_snrmp_batched(int64_t nseg, const int64_t *offsets, const float *x, float p, float *res, void *stream);
+int vnp_dnrmf_batched(int64_t nseg, const int64_t *offsets, int64_t n_total, const double *x, double *res,
+                      void *stream);
+int vnp_snrmf_batched(int64_t nseg, const int64_t *offsets, int64_t n_total, const float *x, float *res,
+                      void *stream);
+int vnp_dnrmp_batched(int64_t nseg, const int64_t *offsets, int64_t n_total, const double *x, double p,
+                      double *res, void *stream);
+int vnp_snrmp_batched(int64_t nseg, const int64_t *offsets, int64_t n_total, const float *x, float p, float *res,
+                      void *stream);
 
 /* Column norms of an m x ncols column-major matrix with leading dimension lda >= m
- * (Sect. 3.1): res[j] = ||A(:, j)||.  Errors: m < 0 -> -1; ncols < 0 -> -2; A == NULL ->
- * -3; lda < max(1, m) -> -4; res == NULL -> -5. */
+ * (Sect. 3.1): res[j] = ||A(:, j)||, each bitwise equal to vnp_dnrmf on that column.
+ * Errors: m < 0 -> -1; ncols < 0 -> -2; A == NULL -> -3; lda < max(1, m) -> -4;
+ * res == NULL -> -5. */
 int vnp_dnrmf_cols(int64_t m, int64_t ncols, const double *A, int64_t lda, double *res, void *stream);
 int vnp_snrmf_cols(int64_t m, int64_t ncols, const float *A, int64_t lda, float *res, void *stream);
 
 /* ------------------------------------------------------------------------------------
- * Plans: a batched workload captured once into a HIP graph with launch shapes chosen
- * by the autotuner (which never changes results), then replayed.  The plan owns its
- * workspace; the caller's buffers must stay valid while the plan is used.
+ * Plans: one batched workload (fixed buffers and segment count) prepared once -- launch
+ * shape chosen by timing candidates on `stream` when autotune is set (the shape never
+ * changes a result), longest segments scheduled first when host offsets are given, and
+ * the setup + batched launches captured in a HIP graph -- then replayed by
+ * vnp_plan_exec.  The plan owns its workspace (so a plan's replays must not overlap
+ * each other); the caller's buffers must stay valid and keep their sizes while the plan
+ * exists; their contents may change between replays.
+ * Errors (create): plan == NULL -> -1; invalid descriptor -> -2; > 0 HIP error.
  * ---------------------------------------------------------------------------------- */
 typedef struct vnp_plan vnp_plan;
 
 typedef struct {
-    int dtype;               /* VNP_F64 or VNP_F32 */
-    double p;                /* 2.0 for the Frobenius norm */
-    int64_t nseg;            /* number of segments */
-    const int64_t *offsets;  /* device, nseg + 1 entries */
-    const int64_t *h_offsets;/* optional host copy of offsets (enables load balancing) */
-    const void *x;           /* device data */
-    void *res;               /* device results, nseg elements */
-    int autotune;            /* 1: time candidate shapes on `stream` during creation */
+    int dtype;                /* VNP_F64 or VNP_F32 */
+    double p;                 /* 2.0 for the Frobenius norm; > 0, may be +inf */
+    int64_t nseg;             /* number of segments */
+    const int64_t *offsets;   /* device, nseg + 1 entries */
+    const int64_t *h_offsets; /* optional host copy of offsets (enables longest-first order) */
+    int64_t n_total;          /* elements in x */
+    const void *x;            /* device data */
+    void *res;                /* device results, nseg elements */
+    int autotune;             /* 1: time candidate shapes on `stream` during creation */
 } vnp_plan_desc;
 
 int vnp_plan_create(vnp_plan **plan, const vnp_plan_desc *desc, void *stream);
 int vnp_plan_exec(vnp_plan *plan, void *stream);
 int vnp_plan_destroy(vnp_plan *plan);
-/* Chosen launch shape: blocks, waves per block, tiles per work item. */
+/* Chosen launch shape: resident blocks, waves per block, tiles per work item. */
 int vnp_plan_info(const vnp_plan *plan, int *blocks, int *waves, int *tiles_per_item);
 
 /* ------------------------------------------------------------------------------------

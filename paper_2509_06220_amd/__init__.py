@@ -46,10 +46,14 @@ def lib():
             "vnp_snrmf": [i64, vp, i64, vp, vp],
             "vnp_dnrmp": [i64, vp, i64, d, vp, vp],
             "vnp_snrmp": [i64, vp, i64, f, vp, vp],
-            "vnp_dnrmf_batched": [i64, vp, vp, vp, vp],
-            "vnp_snrmf_batched": [i64, vp, vp, vp, vp],
-            "vnp_dnrmp_batched": [i64, vp, vp, d, vp, vp],
-            "vnp_snrmp_batched": [i64, vp, vp, f, vp, vp],
+            "vnp_dnrmf_batched": [i64, vp, i64, vp, vp, vp],
+            "vnp_snrmf_batched": [i64, vp, i64, vp, vp, vp],
+            "vnp_dnrmp_batched": [i64, vp, i64, vp, d, vp, vp],
+            "vnp_snrmp_batched": [i64, vp, i64, vp, f, vp, vp],
+            "vnp_plan_create": [vp, vp, vp],
+            "vnp_plan_exec": [vp, vp],
+            "vnp_plan_destroy": [vp],
+            "vnp_plan_info": [vp, vp, vp, vp],
             "vnp_dnrmf_cols": [i64, i64, vp, i64, vp, vp],
             "vnp_snrmf_cols": [i64, i64, vp, i64, vp, vp],
             "vnp_set_launch_shape": [i, i],
@@ -146,16 +150,73 @@ def nrm_batched(x, offsets, p=2.0, out=None, stream=None):
         out = torch.empty(max(nseg, 0), dtype=x.dtype, device=x.device)
     if offsets.dtype != torch.int64 or not offsets.is_cuda:
         raise TypeError("offsets must be a device int64 tensor")
+    if not x.is_contiguous():
+        raise ValueError("x must be contiguous")
     d = x.dtype == torch.float64
     s = _stream(x, stream)
     if p == 2.0:
         fn = "vnp_dnrmf_batched" if d else "vnp_snrmf_batched"
-        rc = getattr(lib(), fn)(nseg, offsets.data_ptr(), x.data_ptr(), out.data_ptr(), s)
+        rc = getattr(lib(), fn)(nseg, offsets.data_ptr(), x.numel(), x.data_ptr(), out.data_ptr(), s)
     else:
         fn = "vnp_dnrmp_batched" if d else "vnp_snrmp_batched"
-        rc = getattr(lib(), fn)(nseg, offsets.data_ptr(), x.data_ptr(), float(p), out.data_ptr(), s)
+        rc = getattr(lib(), fn)(nseg, offsets.data_ptr(), x.numel(), x.data_ptr(), float(p), out.data_ptr(), s)
     _check(fn, rc)
     return out
+
+
+class _PlanDesc(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int), ("p", ctypes.c_double), ("nseg", ctypes.c_int64),
+                ("offsets", ctypes.c_void_p), ("h_offsets", ctypes.c_void_p), ("n_total", ctypes.c_int64),
+                ("x", ctypes.c_void_p), ("res", ctypes.c_void_p), ("autotune", ctypes.c_int)]
+
+
+class Plan:
+    """A batched workload captured once (autotuned shape, HIP graph) and replayed by run().
+
+    The tensors passed here must stay alive (and keep their sizes) while the plan exists;
+    their contents may change between runs."""
+
+    def __init__(self, x, offsets, out=None, p=2.0, h_offsets=None, autotune=True, stream=None):
+        import numpy as np
+        import torch
+
+        self._keep = [x, offsets]
+        nseg = offsets.numel() - 1
+        if out is None:
+            out = torch.empty(max(nseg, 0), dtype=x.dtype, device=x.device)
+        self.out = out
+        self._keep.append(out)
+        hoff = None
+        if h_offsets is not None:
+            hoff = np.ascontiguousarray(np.asarray(h_offsets, dtype=np.int64))
+            self._keep.append(hoff)
+        desc = _PlanDesc(F64 if x.dtype == torch.float64 else F32, float(p), nseg, offsets.data_ptr(),
+                         hoff.ctypes.data if hoff is not None else None, x.numel(), x.data_ptr(), out.data_ptr(),
+                         1 if autotune else 0)
+        self._h = ctypes.c_void_p()
+        _check("vnp_plan_create", lib().vnp_plan_create(ctypes.byref(self._h), ctypes.byref(desc),
+                                                        _stream(x, stream)))
+        self._x = x
+
+    def run(self, stream=None):
+        _check("vnp_plan_exec", lib().vnp_plan_exec(self._h, _stream(self._x, stream)))
+        return self.out
+
+    def info(self):
+        b, w, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check("vnp_plan_info", lib().vnp_plan_info(self._h, ctypes.byref(b), ctypes.byref(w), ctypes.byref(t)))
+        return {"blocks": b.value, "waves_per_block": w.value, "tiles_per_item": t.value}
+
+    def close(self):
+        if self._h:
+            lib().vnp_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 -- interpreter shutdown
+            pass
 
 
 def nrmf_cols(A, m, ncols, lda, out=None, stream=None):

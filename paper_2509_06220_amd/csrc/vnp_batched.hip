@@ -1,0 +1,625 @@
+// Batched norms: many segments in one persistent launch (Novakovic, arXiv 2509.06220,
+// Sect. 3.1: norms of the columns of a multi-dimensional array).
+//
+// Work items are (segment, run of 2^lwt tiles of that segment); waves pull items from
+// an atomic counter, so long and short segments share the GPU without a tail.  Each
+// run's root is an aligned subtree of the segment's canonical tree (the same tree the
+// single-vector call uses), a segment of one run writes its result directly, and the
+// last run of a longer segment to finish (per-segment ticket) reduces the run roots by
+// the fixed tree.  Counters reset themselves, so a captured graph can be replayed
+// without clearing memory.  A setup kernel turns the segment lengths into item offsets
+// (prefix sums over the processing order) and writes +0 for empty segments.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <new>
+#include <numeric>
+#include <utility>
+#include <vector>
+
+#include "../../include/vnp.h"
+#include "vnp_internal.hpp"
+#include "vnp_nodes_p.hpp"
+
+namespace vnp {
+
+// ---------------------------------------------------------------------------------
+// Segment descriptors
+// ---------------------------------------------------------------------------------
+struct SegOffsets {  // segment s = [off[s], off[s+1])
+    const int64_t *off;
+    __device__ int64_t start(int64_t s) const { return off[s]; }
+    __device__ int64_t len(int64_t s) const
+    {
+        const int64_t l = off[s + 1] - off[s];
+        return l > 0 ? l : 0;
+    }
+};
+
+struct SegCols {  // column s of a column-major matrix: [s * lda, s * lda + m)
+    int64_t lda, m;
+    __device__ int64_t start(int64_t s) const { return s * lda; }
+    __device__ int64_t len(int64_t) const { return m; }
+};
+
+template <typename T>
+__device__ __forceinline__ int64_t runs_of(int64_t len, int lwt)
+{
+    constexpr int64_t TE = tile_elems<T>();
+    const int64_t tiles = (len + TE - 1) / TE;
+    return (tiles + ((int64_t)1 << lwt) - 1) >> lwt;
+}
+
+// ---------------------------------------------------------------------------------
+// Setup: item_off[k] = number of items before processing position k (exclusive scan of
+// the run counts over the order), item_off[nseg] = total; res[s] = +0 for empty s.
+// One block of 1024 threads.
+// ---------------------------------------------------------------------------------
+// Segments reaching outside [0, n_total), or more items than the workspace holds
+// (items_cap), make every result NaN and enqueue no work.
+template <typename T, class Seg>
+__global__ void __launch_bounds__(1024)
+    batched_setup_kernel(Seg seg, int64_t nseg, const int32_t *order, int lwt, int64_t n_total, int64_t items_cap,
+                         int64_t *item_off, T *res)
+{
+    __shared__ int64_t part[1024];
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    const int64_t chunk = (nseg + blockDim.x - 1) / blockDim.x;
+    const int64_t k0 = (int64_t)threadIdx.x * chunk;
+    const int64_t k1 = k0 + chunk < nseg ? k0 + chunk : nseg;
+    int64_t sum = 0;
+    for (int64_t k = k0; k < k1; ++k) {
+        const int64_t s = order ? order[k] : k;
+        const int64_t len = seg.len(s);
+        if (len == 0) res[s] = T(0);
+        if (len > 0 && (seg.start(s) < 0 || seg.start(s) > n_total - len)) bad = 1;
+        sum += runs_of<T>(len, lwt);
+    }
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    // inclusive scan of the per-thread sums (Hillis-Steele in LDS)
+    for (int d = 1; d < (int)blockDim.x; d <<= 1) {
+        const int64_t v = threadIdx.x >= (unsigned)d ? part[threadIdx.x - d] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t run = threadIdx.x == 0 ? 0 : part[threadIdx.x - 1];
+    for (int64_t k = k0; k < k1; ++k) {
+        item_off[k] = run;
+        const int64_t s = order ? order[k] : k;
+        run += runs_of<T>(seg.len(s), lwt);
+    }
+    __syncthreads();
+    if (bad || part[blockDim.x - 1] > items_cap) {
+        for (int64_t k = k0; k < k1; ++k) res[order ? order[k] : k] = T(__builtin_nan(""));
+        if (threadIdx.x == blockDim.x - 1) item_off[nseg] = 0;
+    } else if (threadIdx.x == blockDim.x - 1) {
+        item_off[nseg] = part[blockDim.x - 1];
+    }
+}
+
+// Tree over r[0..cnt) (zero-padded to a power of two) by one wave; every lane gets the
+// root.  Chunks of 512 (8 per lane, then the lanes) are aligned subtrees, combined by a
+// wave-uniform binary counter.
+template <class Node>
+__device__ typename Node::T wave_finish(const Node &nd, const typename Node::T *r, int64_t cnt, int lane)
+{
+    using T = typename Node::T;
+    T stk[MAX_LWT + 1];
+    const int64_t nck = (cnt + 511) / 512;
+    for (int64_t ck = 0; ck < nck; ++ck) {
+        const int64_t b0 = ck * 512 + lane * 8;
+        T e[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const bool in = b0 + j < cnt;  // branch-free (see LoadGeneric)
+            const T v = r[in ? b0 + j : 0];
+            e[j] = in ? v : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) e[j] = nd.node(e[2 * j], e[2 * j + 1]);
+        e[0] = nd.node(e[0], e[1]);
+        e[2] = nd.node(e[2], e[3]);
+        T t = uniform(lane_tree(nd, nd.node(e[0], e[2]), lane));
+        const int idx = (int)ck;
+        bool carry = true;
+#pragma unroll
+        for (int l = 0; l < MAX_LWT; ++l) {
+            const bool bit = (idx >> l) & 1;
+            if (carry && bit) t = uniform(nd.node(stk[l], t));
+            if (carry && !bit) stk[l] = t;
+            carry = carry && bit;
+        }
+    }
+    T cur = T(0);
+    bool any = false;
+#pragma unroll
+    for (int l = 0; l < MAX_LWT; ++l) {
+        if ((nck >> l) & 1) {
+            cur = any ? uniform(nd.node(stk[l], cur)) : stk[l];
+            any = true;
+        }
+    }
+    return cur;
+}
+
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffff));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
+    return ((int64_t)hi << 32) | (uint32_t)lo;
+}
+
+// ---------------------------------------------------------------------------------
+// Persistent batched kernel.  ctrs[0]: next item, ctrs[1]: exited waves (both 64-bit,
+// zero at launch and reset by the last wave to exit).
+// ---------------------------------------------------------------------------------
+template <class Node, class Seg, int U>
+__global__ void __launch_bounds__(1024)
+    batched_kernel(Node nd, Seg seg, const typename Node::T *x, int64_t nseg, const int32_t *order,
+                   const int64_t *item_off, int lwt, typename Node::T *roots, unsigned int *seg_cnt,
+                   unsigned long long *ctrs, typename Node::T *res)
+{
+    using T = typename Node::T;
+    constexpr int64_t TE = tile_elems<T>();
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t total = item_off[nseg];
+    const unsigned long long nwaves = (unsigned long long)gridDim.x * (blockDim.x / WAVE);
+    // No lane-dependent branches in this loop: every wave-level step (fetch, ticket,
+    // stores of wave-uniform values) is executed by all lanes, with lane 0 contributing
+    // the increment, so the cross-lane reads always see one converged wave.
+    const unsigned long long one = lane == 0 ? 1ull : 0ull;
+    int64_t item = uniform64((int64_t)atomicAdd(&ctrs[0], one));
+    while (item < total) {
+        // processing position k: the last k with item_off[k] <= item
+        int64_t lo = 0, hi = nseg - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (item_off[mid] <= item)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int64_t k = lo;
+        const int64_t s = order ? order[k] : k;
+        const int64_t r = item - item_off[k];
+        const int64_t start = seg.start(s), len = seg.len(s);
+        const int64_t ntiles = (len + TE - 1) / TE;
+        const int64_t nruns = (ntiles + ((int64_t)1 << lwt) - 1) >> lwt;
+        const T *xs = x + start;
+        T root;
+        if ((((uintptr_t)xs) & 15) == 0)
+            root = wave_root<Node, U, true>(nd, xs, len, 1, r << lwt, ntiles, lwt, lane);
+        else
+            root = wave_root<Node, U, false>(nd, xs, len, 1, r << lwt, ntiles, lwt, lane);
+        if (nruns == 1) {
+            res[s] = nd.finish(root);  // every lane stores the same value
+        } else {
+            roots[item] = root;
+            const unsigned int old = (unsigned int)__builtin_amdgcn_readfirstlane((int)__hip_atomic_fetch_add(
+                &seg_cnt[s], lane == 0 ? 1u : 0u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT));
+            if (old == (unsigned int)(nruns - 1)) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                const T segroot = wave_finish(nd, roots + item_off[k], nruns, lane);
+                res[s] = nd.finish(segroot);
+                __hip_atomic_store(&seg_cnt[s], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        item = uniform64((int64_t)atomicAdd(&ctrs[0], one));
+    }
+    const unsigned long long exited = (unsigned long long)uniform64((int64_t)atomicAdd(&ctrs[1], one));
+    if (exited == nwaves - 1) {
+        __hip_atomic_store(&ctrs[0], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctrs[1], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------------
+struct BatchShape {
+    int lwt;     // log2(tiles per item)
+    int wpb;     // waves per block
+    int blocks;  // resident blocks
+};
+
+struct BatchWorkspace {
+    void *roots = nullptr;
+    size_t roots_cap = 0;  // bytes
+    int64_t *item_off = nullptr;
+    size_t item_cap = 0;  // entries
+    unsigned int *seg_cnt = nullptr;
+    size_t seg_cap = 0;  // entries
+    unsigned long long *ctrs = nullptr;
+};
+
+static int ensure_batch_ws(BatchWorkspace &w, size_t roots_bytes, size_t nseg, hipStream_t st)
+{
+    hipError_t e;
+    if (!w.ctrs) {
+        e = hipMalloc(reinterpret_cast<void **>(&w.ctrs), 256);
+        if (e != hipSuccess) return (int)e;
+        e = hipMemset(w.ctrs, 0, 256);
+        if (e != hipSuccess) return (int)e;
+    }
+    const bool grow_roots = w.roots_cap < roots_bytes, grow_items = w.item_cap < nseg + 1, grow_seg = w.seg_cap < nseg;
+    if ((grow_roots && w.roots) || (grow_items && w.item_off) || (grow_seg && w.seg_cnt)) {
+        e = hipStreamSynchronize(st);  // old buffers may be in use by queued work
+        if (e != hipSuccess) return (int)e;
+    }
+    if (grow_roots) {
+        if (w.roots) (void)hipFree(w.roots);
+        w.roots = nullptr;
+        const size_t b = std::max<size_t>(roots_bytes, 1 << 16);
+        e = hipMalloc(&w.roots, b);
+        if (e != hipSuccess) return (int)e;
+        w.roots_cap = b;
+    }
+    if (grow_items) {
+        if (w.item_off) (void)hipFree(w.item_off);
+        w.item_off = nullptr;
+        const size_t c = std::max<size_t>(nseg + 1, 4096);
+        e = hipMalloc(reinterpret_cast<void **>(&w.item_off), c * sizeof(int64_t));
+        if (e != hipSuccess) return (int)e;
+        w.item_cap = c;
+    }
+    if (grow_seg) {
+        if (w.seg_cnt) (void)hipFree(w.seg_cnt);
+        w.seg_cnt = nullptr;
+        const size_t c = std::max<size_t>(nseg, 4096);
+        e = hipMalloc(reinterpret_cast<void **>(&w.seg_cnt), c * sizeof(unsigned int));
+        if (e != hipSuccess) return (int)e;
+        e = hipMemset(w.seg_cnt, 0, c * sizeof(unsigned int));
+        if (e != hipSuccess) return (int)e;
+        w.seg_cap = c;
+    }
+    return 0;
+}
+
+static void free_batch_ws(BatchWorkspace &w)
+{
+    if (w.roots) (void)hipFree(w.roots);
+    if (w.item_off) (void)hipFree(w.item_off);
+    if (w.seg_cnt) (void)hipFree(w.seg_cnt);
+    if (w.ctrs) (void)hipFree(w.ctrs);
+    w = BatchWorkspace{};
+}
+
+static std::mutex g_bws_mu;
+static std::map<std::pair<int, void *>, BatchWorkspace> g_bws;
+
+int release_batch_workspaces()
+{
+    std::lock_guard<std::mutex> lk(g_bws_mu);
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    for (auto it = g_bws.begin(); it != g_bws.end();) {
+        if (it->first.first == dev) {
+            free_batch_ws(it->second);
+            it = g_bws.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    return 0;
+}
+
+static int g_cus = 0;
+static int cus()
+{
+    if (!g_cus) {
+        int dev = 0, v = 0;
+        g_cus = (hipGetDevice(&dev) == hipSuccess &&
+                 hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+                    ? v
+                    : 256;
+    }
+    return g_cus;
+}
+
+static BatchShape default_batch_shape() { return BatchShape{2, 8, cus() * 2}; }
+
+// Enqueue setup + main kernels for one batched workload (no allocation: ws must be large
+// enough: roots for nseg + total_elems / tile + 1 items).
+template <class Node, class Seg>
+static int enqueue_batched(const Node &nd, const Seg &seg, const typename Node::T *x, int64_t nseg,
+                           int64_t n_total, const int32_t *order, const BatchShape &sh, BatchWorkspace &ws,
+                           typename Node::T *res, hipStream_t st)
+{
+    using T = typename Node::T;
+    const int64_t items_cap = (int64_t)(ws.roots_cap / sizeof(T));
+    hipLaunchKernelGGL((batched_setup_kernel<T, Seg>), dim3(1), dim3(1024), 0, st, seg, nseg, order, sh.lwt,
+                       n_total, items_cap, ws.item_off, res);
+    hipLaunchKernelGGL((batched_kernel<Node, Seg, RowsInFlight<Node>::value>), dim3(sh.blocks),
+                       dim3(sh.wpb * WAVE), 0, st, nd, seg, x, nseg, order, ws.item_off, sh.lwt,
+                       static_cast<T *>(ws.roots), ws.seg_cnt, ws.ctrs, res);
+    return (int)hipGetLastError();
+}
+
+template <class Node, class Seg>
+static int run_batched(const Node &nd, const Seg &seg, const typename Node::T *x, int64_t nseg, int64_t total_elems,
+                       typename Node::T *res, void *stream)
+{
+    using T = typename Node::T;
+    if (nseg == 0) return 0;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const BatchShape sh = default_batch_shape();
+    const int64_t items_cap = nseg + (total_elems + tile_elems<T>() - 1) / tile_elems<T>() + 1;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    std::lock_guard<std::mutex> lk(g_bws_mu);
+    BatchWorkspace &ws = g_bws[std::make_pair(dev, stream)];
+    int rc = ensure_batch_ws(ws, sizeof(T) * (size_t)items_cap, (size_t)nseg, st);
+    if (rc) return rc;
+    return enqueue_batched(nd, seg, x, nseg, total_elems, nullptr, sh, ws, res, st);
+}
+
+template <typename T, class Seg>
+static int run_batched_p(const Seg &seg, const T *x, int64_t nseg, int64_t total, T p, T *res, void *stream,
+                         T cutoff)
+{
+    if (p == T(2)) return run_batched(HypNode<T>{}, seg, x, nseg, total, res, stream);
+    if (p == T(1)) return run_batched(SumNode<T>{}, seg, x, nseg, total, res, stream);
+    if (__builtin_isinf(p) || p >= cutoff) return run_batched(MaxNode<T>{}, seg, x, nseg, total, res, stream);
+    return run_batched(make_lp_node<T>(p), seg, x, nseg, total, res, stream);
+}
+
+// ---------------------------------------------------------------------------------
+// Plans: autotuned shape + captured graph
+// ---------------------------------------------------------------------------------
+struct PlanImpl {
+    int dtype = 0;
+    double p = 2.0;
+    int64_t nseg = 0, n_total = 0;
+    const int64_t *offsets = nullptr;
+    const void *x = nullptr;
+    void *res = nullptr;
+    int32_t *order = nullptr;  // device, processing order (longest segments first) or null
+    BatchShape shape{};
+    BatchWorkspace ws;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+template <class Node>
+static int plan_enqueue(const Node &nd, PlanImpl &P, const BatchShape &sh, hipStream_t st)
+{
+    using T = typename Node::T;
+    return enqueue_batched(nd, SegOffsets{P.offsets}, static_cast<const T *>(P.x), P.nseg, P.n_total, P.order, sh,
+                           P.ws, static_cast<T *>(P.res), st);
+}
+
+template <typename T>
+static int plan_enqueue_p(PlanImpl &P, const BatchShape &sh, hipStream_t st, T cutoff)
+{
+    const T p = (T)P.p;
+    if (p == T(2)) return plan_enqueue(HypNode<T>{}, P, sh, st);
+    if (p == T(1)) return plan_enqueue(SumNode<T>{}, P, sh, st);
+    if (__builtin_isinf(p) || p >= cutoff) return plan_enqueue(MaxNode<T>{}, P, sh, st);
+    return plan_enqueue(make_lp_node<T>(p), P, sh, st);
+}
+
+static int plan_enqueue_any(PlanImpl &P, const BatchShape &sh, hipStream_t st)
+{
+    return P.dtype == VNP_F32 ? plan_enqueue_p<float>(P, sh, st, 0x1p24f) : plan_enqueue_p<double>(P, sh, st, 0x1p53);
+}
+
+// Times candidate shapes (median of 3 launches each) and keeps the fastest.  Every shape
+// computes the same tree, so the choice never changes a result.
+static int autotune(PlanImpl &P, hipStream_t st)
+{
+    std::vector<BatchShape> cands;
+    for (int lwt : {0, 1, 2, 3})
+        for (int wpb : {4, 8})
+            for (int per_cu : {1, 2, 4}) cands.push_back(BatchShape{lwt, wpb, cus() * per_cu * 8 / wpb});
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return (int)hipErrorUnknown;
+    float best = 1e30f;
+    BatchShape best_s = P.shape;
+    int rc = 0;
+    for (const BatchShape &c : cands) {
+        rc = plan_enqueue_any(P, c, st);  // warm-up
+        if (rc) break;
+        float t[3];
+        for (int r = 0; r < 3 && !rc; ++r) {
+            (void)hipEventRecord(a, st);
+            rc = plan_enqueue_any(P, c, st);
+            (void)hipEventRecord(b, st);
+            if (hipEventSynchronize(b) != hipSuccess) rc = (int)hipErrorUnknown;
+            (void)hipEventElapsedTime(&t[r], a, b);
+        }
+        if (rc) break;
+        std::sort(t, t + 3);
+        if (t[1] < best) {
+            best = t[1];
+            best_s = c;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    P.shape = best_s;
+    return rc;
+}
+
+static void plan_free(PlanImpl *P)
+{
+    if (!P) return;
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    if (P->order) (void)hipFree(P->order);
+    free_batch_ws(P->ws);
+    delete P;
+}
+
+}  // namespace vnp
+
+using namespace vnp;
+
+struct vnp_plan {
+    PlanImpl *impl;
+};
+
+extern "C" {
+
+int vnp_plan_create(vnp_plan **plan, const vnp_plan_desc *d, void *stream)
+{
+    if (!plan) return -1;
+    *plan = nullptr;
+    if (!d || (d->dtype != VNP_F64 && d->dtype != VNP_F32) || !(d->p > 0) || d->nseg < 0 || d->n_total < 0 ||
+        (d->nseg > 0 && (!d->offsets || !d->res)) || (d->n_total > 0 && !d->x))
+        return -2;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    PlanImpl *P = new (std::nothrow) PlanImpl;
+    if (!P) return (int)hipErrorOutOfMemory;
+    P->dtype = d->dtype;
+    P->p = d->p;
+    P->nseg = d->nseg;
+    P->n_total = d->n_total;
+    P->offsets = d->offsets;
+    P->x = d->x;
+    P->res = d->res;
+    P->shape = default_batch_shape();
+    const int64_t te = d->dtype == VNP_F32 ? tile_elems<float>() : tile_elems<double>();
+    const size_t esz = d->dtype == VNP_F32 ? 4 : 8;
+    int rc = 0;
+    if (d->h_offsets && d->nseg > 1) {  // longest segments first, so no long item starts late
+        std::vector<int32_t> ord((size_t)d->nseg);
+        std::iota(ord.begin(), ord.end(), 0);
+        const int64_t *o = d->h_offsets;
+        std::stable_sort(ord.begin(), ord.end(),
+                         [o](int32_t u, int32_t v) { return o[u + 1] - o[u] > o[v + 1] - o[v]; });
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&P->order), ord.size() * sizeof(int32_t));
+        if (e == hipSuccess) e = hipMemcpy(P->order, ord.data(), ord.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+        if (e != hipSuccess) rc = (int)e;
+    }
+    const int64_t items_cap = d->nseg + (d->n_total + te - 1) / te + 1;
+    if (!rc) rc = ensure_batch_ws(P->ws, esz * (size_t)items_cap, (size_t)(d->nseg > 0 ? d->nseg : 1), st);
+    if (!rc && d->autotune && d->nseg > 0) rc = autotune(*P, st);
+    if (!rc && d->nseg > 0) {
+        // capture on a private stream (the legacy default stream cannot be captured)
+        hipStream_t cs = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            rc = plan_enqueue_any(*P, P->shape, cs);
+            e = hipStreamEndCapture(cs, &P->graph);
+            if (!rc && e == hipSuccess) e = hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0);
+        }
+        if (cs) (void)hipStreamDestroy(cs);
+        if (!rc && e != hipSuccess) rc = (int)e;
+    }
+    if (rc) {
+        plan_free(P);
+        return rc;
+    }
+    vnp_plan *h = new (std::nothrow) vnp_plan{P};
+    if (!h) {
+        plan_free(P);
+        return (int)hipErrorOutOfMemory;
+    }
+    *plan = h;
+    return 0;
+}
+
+int vnp_plan_exec(vnp_plan *plan, void *stream)
+{
+    if (!plan || !plan->impl) return -1;
+    if (!plan->impl->exec) return 0;  // no segments
+    return (int)hipGraphLaunch(plan->impl->exec, reinterpret_cast<hipStream_t>(stream));
+}
+
+int vnp_plan_destroy(vnp_plan *plan)
+{
+    if (!plan) return -1;
+    plan_free(plan->impl);
+    delete plan;
+    return 0;
+}
+
+int vnp_plan_info(const vnp_plan *plan, int *blocks, int *waves, int *tiles_per_item)
+{
+    if (!plan || !plan->impl) return -1;
+    if (blocks) *blocks = plan->impl->shape.blocks;
+    if (waves) *waves = plan->impl->shape.wpb;
+    if (tiles_per_item) *tiles_per_item = 1 << plan->impl->shape.lwt;
+    return 0;
+}
+
+int vnp_dnrmf_batched(int64_t nseg, const int64_t *offsets, int64_t n_total, const double *x, double *res,
+                      void *stream)
+{
+    if (nseg < 0) return -1;
+    if (nseg > 0 && !offsets) return -2;
+    if (n_total < 0 || n_total > VNP_MAX_N) return -3;
+    if (nseg > 0 && n_total > 0 && !x) return -4;
+    if (nseg > 0 && !res) return -5;
+    return run_batched(HypNode<double>{}, SegOffsets{offsets}, x, nseg, n_total, res, stream);
+}
+
+int vnp_snrmf_batched(int64_t nseg, const int64_t *offsets, int64_t n_total, const float *x, float *res,
+                      void *stream)
+{
+    if (nseg < 0) return -1;
+    if (nseg > 0 && !offsets) return -2;
+    if (n_total < 0 || n_total > VNP_MAX_N) return -3;
+    if (nseg > 0 && n_total > 0 && !x) return -4;
+    if (nseg > 0 && !res) return -5;
+    return run_batched(HypNode<float>{}, SegOffsets{offsets}, x, nseg, n_total, res, stream);
+}
+
+int vnp_dnrmp_batched(int64_t nseg, const int64_t *offsets, int64_t n_total, const double *x, double p,
+                      double *res, void *stream)
+{
+    if (nseg < 0) return -1;
+    if (nseg > 0 && !offsets) return -2;
+    if (n_total < 0 || n_total > VNP_MAX_N) return -3;
+    if (nseg > 0 && n_total > 0 && !x) return -4;
+    if (!(p > 0)) return -5;
+    if (nseg > 0 && !res) return -6;
+    return run_batched_p<double>(SegOffsets{offsets}, x, nseg, n_total, p, res, stream, 0x1p53);
+}
+
+int vnp_snrmp_batched(int64_t nseg, const int64_t *offsets, int64_t n_total, const float *x, float p, float *res,
+                      void *stream)
+{
+    if (nseg < 0) return -1;
+    if (nseg > 0 && !offsets) return -2;
+    if (n_total < 0 || n_total > VNP_MAX_N) return -3;
+    if (nseg > 0 && n_total > 0 && !x) return -4;
+    if (!(p > 0)) return -5;
+    if (nseg > 0 && !res) return -6;
+    return run_batched_p<float>(SegOffsets{offsets}, x, nseg, n_total, p, res, stream, 0x1p24f);
+}
+
+int vnp_dnrmf_cols(int64_t m, int64_t ncols, const double *A, int64_t lda, double *res, void *stream)
+{
+    if (m < 0) return -1;
+    if (ncols < 0) return -2;
+    if (m > 0 && ncols > 0 && !A) return -3;
+    if (lda < (m > 1 ? m : 1)) return -4;
+    if (ncols > 0 && !res) return -5;
+    const int64_t total = ncols > 0 ? (ncols - 1) * lda + m : 0;
+    return run_batched(HypNode<double>{}, SegCols{lda, m}, A, ncols, total, res, stream);
+}
+
+int vnp_snrmf_cols(int64_t m, int64_t ncols, const float *A, int64_t lda, float *res, void *stream)
+{
+    if (m < 0) return -1;
+    if (ncols < 0) return -2;
+    if (m > 0 && ncols > 0 && !A) return -3;
+    if (lda < (m > 1 ? m : 1)) return -4;
+    if (ncols > 0 && !res) return -5;
+    const int64_t total = ncols > 0 ? (ncols - 1) * lda + m : 0;
+    return run_batched(HypNode<float>{}, SegCols{lda, m}, A, ncols, total, res, stream);
+}
+
+}  // extern "C"

@@ -84,7 +84,28 @@ struct MaxNode<float> {
     __device__ float finish(float r) const { return r; }
 };
 
+// Rows per load group (one group is in flight per wave while the previous one is
+// reduced): 8 KiB per wave for the binary64 hypot node, 4 KiB where the node is heavier
+// in registers or arithmetic (measured on MI355X; results never depend on it).
+template <class Node>
+struct RowsInFlight {
+    static constexpr int value = 4;
+};
+template <>
+struct RowsInFlight<HypNode<double>> {
+    static constexpr int value = 8;
+};
+template <>
+struct RowsInFlight<SumNode<double>> {
+    static constexpr int value = 8;
+};
+template <>
+struct RowsInFlight<MaxNode<double>> {
+    static constexpr int value = 8;
+};
+
 int release_workspaces();
+int release_batch_workspaces();
 int set_launch_shape(int wpb, int wt);
 
 }  // namespace vnp

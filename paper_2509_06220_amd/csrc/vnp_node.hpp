@@ -79,7 +79,11 @@ __device__ __forceinline__ double hyp_d(double a, double b)
     // exponent field of the larger operand in [1023 - 380, 1023 + 500)
     const bool fast = (hm - 0x28300000u) < (0x5F300000u - 0x28300000u);
     double r = sqrt_core(__builtin_fma(a, a, b * b));
-    if (!fast) r = hyp_d_scaled(a, b);
+    // wave-uniform branch (no lane-dependent control flow), per-lane choice
+    if (__builtin_amdgcn_ballot_w64(!fast) != 0) {
+        const double rs = hyp_d_scaled(a, b);
+        r = fast ? r : rs;
+    }
     return r;
 }
 

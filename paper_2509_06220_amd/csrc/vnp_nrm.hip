@@ -19,26 +19,6 @@
 
 namespace vnp {
 
-// Rows per load group (one group is in flight per wave while the previous one is
-// reduced): 8 KiB per wave for the binary64 hypot node, 4 KiB where the node is heavier
-// in registers or arithmetic (measured on MI355X; results never depend on it).
-template <class Node>
-struct RowsInFlight {
-    static constexpr int value = 4;
-};
-template <>
-struct RowsInFlight<HypNode<double>> {
-    static constexpr int value = 8;
-};
-template <>
-struct RowsInFlight<SumNode<double>> {
-    static constexpr int value = 8;
-};
-template <>
-struct RowsInFlight<MaxNode<double>> {
-    static constexpr int value = 8;
-};
-
 // ---------------------------------------------------------------------------------
 // Kernel
 // ---------------------------------------------------------------------------------
@@ -308,6 +288,10 @@ uint32_t vnp_tree_id(int dtype)
 
 const char *vnp_version(void) { return "vnp 0.1 (gfx950)"; }
 
-int vnp_finalize(void) { return release_workspaces(); }
+int vnp_finalize(void)
+{
+    release_batch_workspaces();
+    return release_workspaces();
+}
 
 }  // extern "C"

@@ -71,18 +71,22 @@ struct LoadFast {  // contiguous, 16-byte aligned, full tile
 };
 
 template <typename T>
-struct LoadGeneric {  // any stride / alignment / partial tile; zero beyond n
+struct LoadGeneric {  // any stride / alignment / partial tile; zero beyond n (n >= 1)
     using V = typename Vec<T>::V;
     const T *x;  // logical element i is x[i * inc]
     int64_t inc, n, base;
     __device__ V operator()(int r, int lane) const
     {
-        V v = Vec<T>::zero();
+        V v;
         const int64_t i0 = base + (int64_t)r * (WAVE * Vec<T>::N) + lane * Vec<T>::N;
 #pragma unroll
         for (int c = 0; c < Vec<T>::N; ++c) {
+            // branch-free: lanes past the end read element 0 and keep a zero, so no
+            // lane-dependent control flow precedes the wave-wide steps that follow
             const int64_t i = i0 + c;
-            v[c] = i < n ? x[i * inc] : T(0);
+            const bool in = i < n;
+            const T e = x[(in ? i : 0) * inc];
+            v[c] = in ? e : T(0);
         }
         return v;
     }
@@ -330,7 +334,11 @@ __device__ T block_finish(const Node &nd, T *r, int64_t count, T *sbuf)
             const int64_t b0 = ck * chunk + (int64_t)threadIdx.x * 8;
             T e[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) e[j] = (b0 + j < count) ? r[b0 + j] : T(0);
+            for (int j = 0; j < 8; ++j) {
+                const bool in = b0 + j < count;
+                const T v = r[in ? b0 + j : 0];
+                e[j] = in ? v : T(0);
+            }
 #pragma unroll
             for (int j = 0; j < 4; ++j) e[j] = nd.node(e[2 * j], e[2 * j + 1]);
             e[0] = nd.node(e[0], e[1]);

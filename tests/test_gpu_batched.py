@@ -1,0 +1,125 @@
+"""Batched norms, column norms and plans: every segment bitwise equal to the single-vector
+call (same canonical tree), graph replays equal to eager calls, invalid offsets rejected."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import vnp_gen
+from gpu_util import assert_parity, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+vnp = pytest.importorskip("paper_2509_06220_amd")
+
+
+def _segments(seed, count, maxlog=18):
+    L = vnp_gen.log_uniform_lengths(count, 0, maxlog, seed=seed)
+    L[::7] = 0  # some empty segments
+    L[1] = 1
+    L[2] = 8192 * 3 + 17
+    off = np.zeros(count + 1, dtype=np.int64)
+    off[1:] = np.cumsum(L)
+    return off
+
+
+def _plain(x, off, s, p=2.0):
+    seg = x[int(off[s]):int(off[s + 1])]
+    if seg.numel() == 0:
+        return 0.0
+    r = vnp.nrmf(seg) if p == 2.0 else vnp.nrmp(seg, p)
+    return r.item()
+
+
+@pytest.mark.parametrize("fmt", ["f64", "f32"])
+@pytest.mark.parametrize("p", [2.0, 1.0, 3.0, math.inf])
+def test_batched_bitwise_equals_plain(fmt, p):
+    off = _segments(1, 300)
+    n = int(off[-1])
+    x = to_dev(vnp_gen.host_fill(n, dtype=fmt, kind="u11exp", lo=-30, hi=30, seed=2))
+    res = vnp.nrm_batched(x, to_dev(off), p=p)
+    torch.cuda.synchronize()
+    r = res.cpu().numpy()
+    print(f"batched {fmt} p={p}: {len(off) - 1} segments, {n} elements", flush=True)
+    for s in range(len(off) - 1):
+        assert r[s] == _plain(x, off, s, p) or (math.isnan(r[s]) and math.isnan(_plain(x, off, s, p))), s
+
+
+@pytest.mark.parametrize("fmt", ["f64", "f32"])
+def test_batched_against_oracle(fmt):
+    off = _segments(3, 64, maxlog=16)
+    xh = vnp_gen.host_fill(int(off[-1]), dtype=fmt, kind="u11exp", lo=-30, hi=30, seed=4)
+    r = vnp.nrm_batched(to_dev(xh), to_dev(off)).cpu().numpy()
+    for s in range(len(off) - 1):
+        seg = xh[off[s]:off[s + 1]]
+        assert_parity(r[s], oracle.nrmf(seg, "A"), max(seg.size, 1), fmt, f"segment {s}")
+
+
+@pytest.mark.parametrize("fmt", ["f64", "f32"])
+def test_node_via_two_element_segments(fmt):
+    # segments of length 2 evaluate exactly one leaf node: compare it with cr_hypot
+    dt = np.float64 if fmt == "f64" else np.float32
+    rng = np.random.default_rng(5)
+    k = 20000
+    a = (rng.random(k) + 0.5) * np.exp2(rng.integers(-60, 60, k))
+    b = a * np.exp2(-rng.random(k) * 30)
+    pairs = np.stack([a, -b], axis=1).astype(dt).reshape(-1)
+    off = np.arange(0, 2 * k + 1, 2, dtype=np.int64)
+    r = vnp.nrm_batched(to_dev(pairs), to_dev(off)).cpu().numpy()
+    eps = 2.0 ** -53 if fmt == "f64" else 2.0 ** -24
+    worst = 0.0
+    for i in range(k):
+        x0, x1 = float(pairs[2 * i]), float(pairs[2 * i + 1])
+        c = oracle.cr_hypot(x0, x1) if fmt == "f64" else oracle.cr_hypotf(x0, x1)
+        worst = max(worst, abs(float(r[i]) - c) / c / eps)
+    # binary64 node: relative error <= (1 + eps)^2 - 1 from the exact value, so within
+    # 3 eps of the correctly rounded one; binary32 node: within 1.0001 eps (nearly correctly rounded)
+    assert worst <= (3.0 if fmt == "f64" else 1.0001), worst
+    z = vnp.nrm_batched(to_dev(np.stack([a.astype(dt), np.zeros(k, dt)], 1).reshape(-1)), to_dev(off)).cpu().numpy()
+    assert np.array_equal(z, a.astype(dt))  # node(a, 0) = |a| exactly
+
+
+@pytest.mark.parametrize("fmt", ["f64", "f32"])
+def test_column_norms(fmt):
+    m, ncols, lda = 20000, 37, 20011
+    A = vnp_gen.host_fill(lda * ncols, dtype=fmt, kind="exp", lo=-10, hi=10, seed=6)
+    d = to_dev(A)
+    r = vnp.nrmf_cols(d, m, ncols, lda).cpu().numpy()
+    for j in range(ncols):
+        assert r[j] == vnp.nrmf(d[j * lda:j * lda + m]).item()
+
+
+@pytest.mark.parametrize("fmt", ["f64", "f32"])
+def test_plan_graph_replays(fmt):
+    off = _segments(7, 500)
+    n = int(off[-1])
+    x = to_dev(vnp_gen.host_fill(n, dtype=fmt, kind="u11exp", lo=-30, hi=30, seed=8))
+    doff = to_dev(off)
+    plan = vnp.Plan(x, doff, h_offsets=off, autotune=True)
+    print("plan shape", plan.info(), flush=True)
+    for rep in range(4):
+        vnp_gen.dev_fill(x, kind="u11exp", lo=-30, hi=30, seed=100 + rep)
+        got = plan.run().clone()
+        torch.cuda.synchronize()
+        ref = vnp.nrm_batched(x, doff)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), rep
+    plan.close()
+
+
+def test_invalid_offsets_give_nan_without_reading():
+    x = torch.ones(1000, dtype=torch.float64, device="cuda")
+    off = to_dev(np.array([0, 10, 5000], dtype=np.int64))  # second segment runs past the end
+    r = vnp.nrm_batched(x, off).cpu().numpy()
+    assert np.all(np.isnan(r))
+    ok = vnp.nrm_batched(x, to_dev(np.array([0, 10, 1000], dtype=np.int64))).cpu().numpy()
+    assert ok[0] == vnp.nrmf(x[:10]).item() and ok[1] == vnp.nrmf(x[10:]).item()
+
+
+def test_batched_argument_errors():
+    L = vnp.lib()
+    assert L.vnp_dnrmf_batched(-1, 0, 0, 0, 0, None) == -1
+    assert L.vnp_dnrmf_batched(3, 0, 10, 0, 0, None) == -2
+    assert L.vnp_dnrmf_cols(5, 2, 1, 4, 1, None) == -4
