@@ -58,6 +58,14 @@ def lib():
             "vnp_snrmf_cols": [i64, i64, vp, i64, vp, vp],
             "vnp_set_launch_shape": [i, i],
             "vnp_finalize": [],
+            "vnp_server_create": [vp, vp],
+            "vnp_server_destroy": [vp],
+            "vnp_server_alloc": [vp, i64, vp],
+            "vnp_server_free": [vp, vp],
+            "vnp_server_submit": [vp, vp, vp],
+            "vnp_server_poll": [vp, ctypes.c_uint64, vp],
+            "vnp_server_wait": [vp, ctypes.c_uint64, i64, vp],
+            "vnp_server_get_stats": [vp, vp],
         }
         for name, args in sig.items():
             if hasattr(L, name):
@@ -70,6 +78,8 @@ def lib():
         L.vnp_tree_id.argtypes = [ctypes.c_int]
         L.vnp_tile_elems.restype = ctypes.c_int64
         L.vnp_tile_elems.argtypes = [ctypes.c_int]
+        L.vnp_server_clock_ns.restype = ctypes.c_int64
+        L.vnp_server_clock_ns.argtypes = []
         _lib = L
     return _lib
 
@@ -228,6 +238,94 @@ def nrmf_cols(A, m, ncols, lda, out=None, stream=None):
     fn = "vnp_dnrmf_cols" if A.dtype == torch.float64 else "vnp_snrmf_cols"
     _check(fn, getattr(lib(), fn)(m, ncols, A.data_ptr(), lda, out.data_ptr(), _stream(A, stream)))
     return out
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("pool_bytes", ctypes.c_int64), ("max_batch", ctypes.c_int), ("streams", ctypes.c_int),
+                ("max_wait_us", ctypes.c_int), ("inject_failure_every", ctypes.c_int)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int), ("p", ctypes.c_double), ("n", ctypes.c_int64), ("x", ctypes.c_void_p),
+                ("incx", ctypes.c_int64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("value", ctypes.c_double), ("status", ctypes.c_int), ("t_submit_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "rejected", "batches", "launches",
+                                              "failed_batches", "max_batch_seen", "pool_free_bytes", "pool_bytes",
+                                              "pending", "in_flight")]
+
+
+class Server:
+    """Continuous-batching request server (include/vnp_server.h)."""
+
+    def __init__(self, pool_bytes=1 << 30, max_batch=1024, streams=4, max_wait_us=0, inject_failure_every=0):
+        self.cfg = ServerConfig(pool_bytes, max_batch, streams, max_wait_us, inject_failure_every)
+        self._h = ctypes.c_void_p()
+        _check("vnp_server_create", lib().vnp_server_create(ctypes.byref(self._h), ctypes.byref(self.cfg)))
+
+    @property
+    def handle(self):
+        return self._h.value
+
+    def alloc(self, nbytes):
+        """Device pointer from the pool, or None when the pool is full (back-pressure)."""
+        p = ctypes.c_void_p()
+        rc = lib().vnp_server_alloc(self._h, int(nbytes), ctypes.byref(p))
+        if rc == EAGAIN:
+            return None
+        _check("vnp_server_alloc", rc)
+        return p.value
+
+    def free(self, ptr):
+        _check("vnp_server_free", lib().vnp_server_free(self._h, ctypes.c_void_p(ptr)))
+
+    def submit(self, ptr, n, dtype=F64, p=2.0, incx=1):
+        req = Request(dtype, float(p), int(n), ptr, int(incx))
+        t = ctypes.c_uint64()
+        _check("vnp_server_submit", lib().vnp_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
+        return t.value
+
+    def wait(self, ticket, timeout_us=-1):
+        r = Result()
+        rc = lib().vnp_server_wait(self._h, ticket, int(timeout_us), ctypes.byref(r))
+        if rc == EPENDING:
+            return None
+        _check("vnp_server_wait", rc)
+        return r
+
+    def poll(self, ticket):
+        r = Result()
+        rc = lib().vnp_server_poll(self._h, ticket, ctypes.byref(r))
+        if rc == EPENDING:
+            return None
+        _check("vnp_server_poll", rc)
+        return r
+
+    def stats(self):
+        s = ServerStats()
+        _check("vnp_server_get_stats", lib().vnp_server_get_stats(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._h:
+            lib().vnp_server_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001 -- interpreter shutdown
+            pass
+
+
+def server_clock_ns():
+    return lib().vnp_server_clock_ns()
 
 
 def set_launch_shape(waves_per_block=0, tiles_per_wave=0):

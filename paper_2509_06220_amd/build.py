@@ -61,6 +61,9 @@ def build_gen(verbose: bool = False):
     subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", host_src, "-o",
                            host_lib + ".tmp", "-lm"])
     os.replace(host_lib + ".tmp", host_lib)
+    lg_src, lg_lib = os.path.join(gen, "loadgen.cpp"), os.path.join(gen, "libvnp_loadgen.so")
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread", lg_src, "-o", lg_lib + ".tmp"])
+    os.replace(lg_lib + ".tmp", lg_lib)
 
 
 if __name__ == "__main__":

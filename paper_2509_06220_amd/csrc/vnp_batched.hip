@@ -30,20 +30,44 @@ namespace vnp {
 // ---------------------------------------------------------------------------------
 // Segment descriptors
 // ---------------------------------------------------------------------------------
-struct SegOffsets {  // segment s = [off[s], off[s+1])
+// A descriptor gives, for segment s: len(s), base(x, s) (the address of its logical
+// element 0), inc(s) (the stride between logical elements) and ok(s, n_total) (the
+// segment lies inside the buffer the caller declared).
+struct SegOffsets {  // segment s = x[off[s] .. off[s+1])
     const int64_t *off;
-    __device__ int64_t start(int64_t s) const { return off[s]; }
     __device__ int64_t len(int64_t s) const
     {
         const int64_t l = off[s + 1] - off[s];
         return l > 0 ? l : 0;
     }
+    template <typename T>
+    __device__ const T *base(const T *x, int64_t s) const { return x + off[s]; }
+    __device__ int64_t inc(int64_t) const { return 1; }
+    __device__ bool ok(int64_t s, int64_t n_total) const
+    {
+        const int64_t l = len(s);
+        return l == 0 || (off[s] >= 0 && off[s] <= n_total - l);
+    }
 };
 
-struct SegCols {  // column s of a column-major matrix: [s * lda, s * lda + m)
+struct SegCols {  // column s of a column-major matrix: x[s * lda .. s * lda + m)
     int64_t lda, m;
-    __device__ int64_t start(int64_t s) const { return s * lda; }
     __device__ int64_t len(int64_t) const { return m; }
+    template <typename T>
+    __device__ const T *base(const T *x, int64_t s) const { return x + s * lda; }
+    __device__ int64_t inc(int64_t) const { return 1; }
+    __device__ bool ok(int64_t, int64_t) const { return true; }
+};
+
+struct SegList {  // independent requests: len[s] elements at ptr[s] with stride inc[s]
+    const void *const *ptr;  // address of logical element 0 (already moved for inc < 0)
+    const int64_t *lens;
+    const int64_t *incs;
+    __device__ int64_t len(int64_t s) const { return lens[s] > 0 ? lens[s] : 0; }
+    template <typename T>
+    __device__ const T *base(const T *, int64_t s) const { return static_cast<const T *>(ptr[s]); }
+    __device__ int64_t inc(int64_t s) const { return incs[s]; }
+    __device__ bool ok(int64_t, int64_t) const { return true; }
 };
 
 template <typename T>
@@ -78,7 +102,7 @@ __global__ void __launch_bounds__(1024)
         const int64_t s = order ? order[k] : k;
         const int64_t len = seg.len(s);
         if (len == 0) res[s] = T(0);
-        if (len > 0 && (seg.start(s) < 0 || seg.start(s) > n_total - len)) bad = 1;
+        if (!seg.ok(s, n_total)) bad = 1;
         sum += runs_of<T>(len, lwt);
     }
     part[threadIdx.x] = sum;
@@ -190,15 +214,15 @@ __global__ void __launch_bounds__(1024)
         const int64_t k = lo;
         const int64_t s = order ? order[k] : k;
         const int64_t r = item - item_off[k];
-        const int64_t start = seg.start(s), len = seg.len(s);
+        const int64_t len = seg.len(s), inc = seg.inc(s);
         const int64_t ntiles = (len + TE - 1) / TE;
         const int64_t nruns = (ntiles + ((int64_t)1 << lwt) - 1) >> lwt;
-        const T *xs = x + start;
+        const T *xs = seg.base(x, s);
         T root;
-        if ((((uintptr_t)xs) & 15) == 0)
+        if (inc == 1 && (((uintptr_t)xs) & 15) == 0)
             root = wave_root<Node, U, true>(nd, xs, len, 1, r << lwt, ntiles, lwt, lane);
         else
-            root = wave_root<Node, U, false>(nd, xs, len, 1, r << lwt, ntiles, lwt, lane);
+            root = wave_root<Node, U, false>(nd, xs, len, inc, r << lwt, ntiles, lwt, lane);
         if (nruns == 1) {
             res[s] = nd.finish(root);  // every lane stores the same value
         } else {
@@ -224,22 +248,6 @@ __global__ void __launch_bounds__(1024)
 // ---------------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------------
-struct BatchShape {
-    int lwt;     // log2(tiles per item)
-    int wpb;     // waves per block
-    int blocks;  // resident blocks
-};
-
-struct BatchWorkspace {
-    void *roots = nullptr;
-    size_t roots_cap = 0;  // bytes
-    int64_t *item_off = nullptr;
-    size_t item_cap = 0;  // entries
-    unsigned int *seg_cnt = nullptr;
-    size_t seg_cap = 0;  // entries
-    unsigned long long *ctrs = nullptr;
-};
-
 static int ensure_batch_ws(BatchWorkspace &w, size_t roots_bytes, size_t nseg, hipStream_t st)
 {
     hipError_t e;
@@ -371,6 +379,38 @@ static int run_batched_p(const Seg &seg, const T *x, int64_t nseg, int64_t total
     if (__builtin_isinf(p) || p >= cutoff) return run_batched(MaxNode<T>{}, seg, x, nseg, total, res, stream);
     return run_batched(make_lp_node<T>(p), seg, x, nseg, total, res, stream);
 }
+
+// Enqueue one class of independent requests (same dtype and p) from the server: nseg
+// requests described by device arrays (ptrs, lens, incs), results to res (T array).
+int enqueue_requests(int dtype, double p, int64_t nseg, const void *const *ptrs, const int64_t *lens,
+                     const int64_t *incs, int64_t max_elems, void *res, BatchWorkspace &ws, hipStream_t st)
+{
+    const SegList seg{ptrs, lens, incs};
+    const BatchShape sh = default_batch_shape();
+    if (dtype == VNP_F32) {
+        const int64_t cap = nseg + (max_elems + tile_elems<float>() - 1) / tile_elems<float>() + 1;
+        int rc = ensure_batch_ws(ws, sizeof(float) * (size_t)cap, (size_t)nseg, st);
+        if (rc) return rc;
+        const float pf = (float)p;
+        float *r = static_cast<float *>(res);
+        if (pf == 2.0f) return enqueue_batched(HypNode<float>{}, seg, (const float *)nullptr, nseg, 0, nullptr, sh, ws, r, st);
+        if (pf == 1.0f) return enqueue_batched(SumNode<float>{}, seg, (const float *)nullptr, nseg, 0, nullptr, sh, ws, r, st);
+        if (__builtin_isinf(pf) || pf >= 0x1p24f)
+            return enqueue_batched(MaxNode<float>{}, seg, (const float *)nullptr, nseg, 0, nullptr, sh, ws, r, st);
+        return enqueue_batched(make_lp_node<float>(pf), seg, (const float *)nullptr, nseg, 0, nullptr, sh, ws, r, st);
+    }
+    const int64_t cap = nseg + (max_elems + tile_elems<double>() - 1) / tile_elems<double>() + 1;
+    int rc = ensure_batch_ws(ws, sizeof(double) * (size_t)cap, (size_t)nseg, st);
+    if (rc) return rc;
+    double *r = static_cast<double *>(res);
+    if (p == 2.0) return enqueue_batched(HypNode<double>{}, seg, (const double *)nullptr, nseg, 0, nullptr, sh, ws, r, st);
+    if (p == 1.0) return enqueue_batched(SumNode<double>{}, seg, (const double *)nullptr, nseg, 0, nullptr, sh, ws, r, st);
+    if (__builtin_isinf(p) || p >= 0x1p53)
+        return enqueue_batched(MaxNode<double>{}, seg, (const double *)nullptr, nseg, 0, nullptr, sh, ws, r, st);
+    return enqueue_batched(make_lp_node<double>(p), seg, (const double *)nullptr, nseg, 0, nullptr, sh, ws, r, st);
+}
+
+void release_batch_ws(BatchWorkspace &w) { free_batch_ws(w); }
 
 // ---------------------------------------------------------------------------------
 // Plans: autotuned shape + captured graph

@@ -104,8 +104,28 @@ struct RowsInFlight<MaxNode<double>> {
     static constexpr int value = 8;
 };
 
+struct BatchShape {
+    int lwt;     // log2(tiles per item)
+    int wpb;     // waves per block
+    int blocks;  // resident blocks
+};
+
+struct BatchWorkspace {
+    void *roots = nullptr;
+    size_t roots_cap = 0;  // bytes
+    int64_t *item_off = nullptr;
+    size_t item_cap = 0;  // entries
+    unsigned int *seg_cnt = nullptr;
+    size_t seg_cap = 0;  // entries
+    unsigned long long *ctrs = nullptr;
+};
+
 int release_workspaces();
 int release_batch_workspaces();
+// Batched launch of independent requests of one class (dtype, p); used by the server.
+int enqueue_requests(int dtype, double p, int64_t nseg, const void *const *ptrs, const int64_t *lens,
+                     const int64_t *incs, int64_t max_elems, void *res, BatchWorkspace &ws, hipStream_t st);
+void release_batch_ws(BatchWorkspace &w);
 int set_launch_shape(int wpb, int wt);
 
 }  // namespace vnp

@@ -1,0 +1,479 @@
+// Request server: continuous batching of norm requests (see include/vnp_server.h).
+//
+// One batcher thread owns the GPU side.  Clients submit requests (host bookkeeping
+// only); the batcher moves pending requests into a free stream slot, uploads their
+// descriptors in one copy, enqueues one batched launch per (dtype, p) class, copies
+// the results back into pinned memory and records an event.  Finished slots are
+// detected by polling their events, results are posted to the tickets and waiters are
+// woken.  With several slots, requests that arrive while batches run are launched on
+// another stream and overlap on the device.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/vnp_server.h"
+#include "vnp_internal.hpp"
+
+namespace {
+
+int64_t now_ns()
+{
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+// First-fit allocator over one device allocation, 256-byte granules, with coalescing.
+struct Pool {
+    char *base = nullptr;
+    uint64_t size = 0;
+    std::map<uint64_t, uint64_t> free_;  // offset -> size
+    std::map<uint64_t, uint64_t> used_;  // offset -> size
+    uint64_t free_bytes = 0;
+
+    void init(char *b, uint64_t s)
+    {
+        base = b;
+        size = s;
+        free_.clear();
+        used_.clear();
+        free_[0] = s;
+        free_bytes = s;
+    }
+    void *alloc(uint64_t bytes)
+    {
+        const uint64_t need = (bytes + 255) & ~uint64_t(255);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= need) {
+                const uint64_t off = it->first, rest = it->second - need;
+                free_.erase(it);
+                if (rest) free_[off + need] = rest;
+                used_[off] = need;
+                free_bytes -= need;
+                return base + off;
+            }
+        }
+        return nullptr;
+    }
+    bool release(void *p)
+    {
+        if (!p || static_cast<char *>(p) < base) return false;
+        const uint64_t off = (uint64_t)(static_cast<char *>(p) - base);
+        auto u = used_.find(off);
+        if (u == used_.end()) return false;
+        uint64_t start = off, len = u->second;
+        used_.erase(u);
+        free_bytes += len;
+        auto nx = free_.lower_bound(start);
+        if (nx != free_.end() && nx->first == start + len) {
+            len += nx->second;
+            nx = free_.erase(nx);
+        }
+        if (nx != free_.begin()) {
+            auto pv = std::prev(nx);
+            if (pv->first + pv->second == start) {
+                start = pv->first;
+                len += pv->second;
+                free_.erase(pv);
+            }
+        }
+        free_[start] = len;
+        return true;
+    }
+};
+
+struct Pending {
+    uint64_t ticket;
+    vnp_request req;
+    int64_t t_submit;
+    bool solo;  // rerun alone after an injected batch failure
+};
+
+struct Ticket {
+    vnp_result r;
+    bool done;
+};
+
+struct Slot {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    vnp::BatchWorkspace ws;
+    char *d_desc = nullptr, *h_desc = nullptr;  // [ptrs | lens | incs], cap entries each
+    char *d_res = nullptr, *h_res = nullptr;    // [double | float], cap entries each
+    std::vector<Pending> reqs;
+    bool busy = false;
+};
+
+struct Class {
+    int dtype;
+    double p;
+    int64_t a, b;  // request range [a, b) after sorting
+};
+
+bool same_class(const vnp_request &u, const vnp_request &v)
+{
+    return u.dtype == v.dtype && (u.p == v.p || (u.p != u.p && v.p != v.p));
+}
+
+}  // namespace
+
+struct vnp_server {
+    vnp_server_config cfg{};
+    int device = 0;
+    Pool pool;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Pending> pending;
+    std::unordered_map<uint64_t, Ticket> tickets;
+    std::vector<Slot> slots;
+    std::thread worker;
+    bool stop = false;
+    uint64_t next_ticket = 1;
+    vnp_server_stats st{};
+    int64_t batch_counter = 0;
+
+    void worker_loop();
+    int launch(Slot &s, std::vector<Pending> &reqs, int *nlaunch);
+    void complete(Slot &s, int status);
+};
+
+int vnp_server::launch(Slot &s, std::vector<Pending> &reqs, int *nlaunch)
+{
+    *nlaunch = 0;
+    const size_t cap = (size_t)cfg.max_batch;
+    std::stable_sort(reqs.begin(), reqs.end(), [](const Pending &u, const Pending &v) {
+        if (u.req.dtype != v.req.dtype) return u.req.dtype < v.req.dtype;
+        return u.req.p < v.req.p;
+    });
+    void **hp = reinterpret_cast<void **>(s.h_desc);
+    int64_t *hl = reinterpret_cast<int64_t *>(s.h_desc + cap * 8);
+    int64_t *hi = reinterpret_cast<int64_t *>(s.h_desc + cap * 16);
+    std::vector<Class> classes;
+    for (size_t i = 0; i < reqs.size(); ++i) {
+        const vnp_request &q = reqs[i].req;
+        const size_t esz = q.dtype == VNP_F32 ? 4 : 8;
+        const char *x = static_cast<const char *>(q.x);
+        hp[i] = const_cast<char *>(q.incx >= 0 || q.n <= 0 ? x : x + (size_t)((q.n - 1) * (-q.incx)) * esz);
+        hl[i] = q.n;
+        hi[i] = q.incx;
+        if (classes.empty() || !same_class(reqs[classes.back().a].req, q))
+            classes.push_back(Class{q.dtype, q.p, (int64_t)i, (int64_t)i + 1});
+        else
+            classes.back().b = (int64_t)i + 1;
+    }
+    hipError_t e = hipMemcpyAsync(s.d_desc, s.h_desc, cap * 24, hipMemcpyHostToDevice, s.st);
+    if (e != hipSuccess) return (int)e;
+    void **dp = reinterpret_cast<void **>(s.d_desc);
+    int64_t *dl = reinterpret_cast<int64_t *>(s.d_desc + cap * 8);
+    int64_t *di = reinterpret_cast<int64_t *>(s.d_desc + cap * 16);
+    for (const Class &c : classes) {
+        int64_t elems = 0;
+        for (int64_t i = c.a; i < c.b; ++i) elems += std::max<int64_t>(hl[i], 0);
+        void *res = c.dtype == VNP_F32 ? static_cast<void *>(s.d_res + cap * 8 + (size_t)c.a * 4)
+                                       : static_cast<void *>(s.d_res + (size_t)c.a * 8);
+        const int rc = vnp::enqueue_requests(c.dtype, c.p, c.b - c.a, (const void *const *)(dp + c.a), dl + c.a,
+                                             di + c.a, elems, res, s.ws, s.st);
+        if (rc) return rc;
+        *nlaunch += 1;
+    }
+    e = hipMemcpyAsync(s.h_res, s.d_res, cap * 12, hipMemcpyDeviceToHost, s.st);
+    if (e == hipSuccess) e = hipEventRecord(s.ev, s.st);
+    return (int)e;
+}
+
+// Posts the slot's results (status 0) or the error to its tickets.  Called with mu held.
+void vnp_server::complete(Slot &s, int status)
+{
+    const size_t cap = (size_t)cfg.max_batch;
+    const double *rd = reinterpret_cast<const double *>(s.h_res);
+    const float *rf = reinterpret_cast<const float *>(s.h_res + cap * 8);
+    const int64_t t = now_ns();
+    for (size_t i = 0; i < s.reqs.size(); ++i) {
+        auto it = tickets.find(s.reqs[i].ticket);
+        if (it == tickets.end()) continue;
+        Ticket &tk = it->second;
+        tk.r.status = status;
+        tk.r.value = status ? __builtin_nan("") : (s.reqs[i].req.dtype == VNP_F32 ? (double)rf[i] : rd[i]);
+        tk.r.t_done_ns = t;
+        tk.done = true;
+        st.completed += 1;
+    }
+    s.reqs.clear();
+    s.busy = false;
+    cv_done.notify_all();
+}
+
+void vnp_server::worker_loop()
+{
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+        bool any_busy = false;
+        for (Slot &s : slots) {
+            if (!s.busy) continue;
+            const hipError_t q = hipEventQuery(s.ev);
+            if (q == hipSuccess)
+                complete(s, 0);
+            else if (q != hipErrorNotReady)
+                complete(s, (int)q);
+            else
+                any_busy = true;
+        }
+        if (stop && !any_busy) break;
+        Slot *free_slot = nullptr;
+        for (Slot &s : slots)
+            if (!s.busy) {
+                free_slot = &s;
+                break;
+            }
+        bool go = false;
+        int64_t wait_ns = -1;
+        if (!stop && free_slot && !pending.empty()) {
+            const int64_t age = now_ns() - pending.front().t_submit;
+            go = cfg.max_wait_us == 0 || (int64_t)pending.size() >= cfg.max_batch ||
+                 age >= (int64_t)cfg.max_wait_us * 1000 || pending.front().solo;
+            if (!go) wait_ns = (int64_t)cfg.max_wait_us * 1000 - age;
+        }
+        if (go) {
+            std::vector<Pending> batch;
+            if (pending.front().solo) {
+                batch.push_back(pending.front());
+                pending.pop_front();
+            } else {
+                while (!pending.empty() && (int)batch.size() < cfg.max_batch && !pending.front().solo) {
+                    batch.push_back(pending.front());
+                    pending.pop_front();
+                }
+            }
+            Slot &s = *free_slot;
+            s.busy = true;
+            const int64_t bno = ++batch_counter;
+            st.batches += 1;
+            st.max_batch_seen = std::max<int64_t>(st.max_batch_seen, (int64_t)batch.size());
+            if (cfg.inject_failure_every > 0 && bno % cfg.inject_failure_every == 0 && batch.size() > 1) {
+                // injected failure: nothing is launched; each request is rerun alone
+                st.failed_batches += 1;
+                for (auto it = batch.rbegin(); it != batch.rend(); ++it) {
+                    Pending p = *it;
+                    p.solo = true;
+                    pending.push_front(p);
+                }
+                s.busy = false;
+                continue;
+            }
+            lk.unlock();
+            int nl = 0;
+            const int rc = launch(s, batch, &nl);
+            if (rc) (void)hipStreamSynchronize(s.st);  // nothing of a failed batch may still run
+            lk.lock();
+            st.launches += nl;
+            s.reqs = std::move(batch);
+            if (rc) complete(s, rc);
+            continue;
+        }
+        if (any_busy)
+            cv_work.wait_for(lk, std::chrono::microseconds(10));
+        else if (wait_ns > 0)
+            cv_work.wait_for(lk, std::chrono::nanoseconds(wait_ns));
+        else
+            cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+    }
+}
+
+static void free_slots(vnp_server *s)
+{
+    for (Slot &sl : s->slots) {
+        if (sl.st) (void)hipStreamSynchronize(sl.st);
+        vnp::release_batch_ws(sl.ws);
+        if (sl.d_desc) (void)hipFree(sl.d_desc);
+        if (sl.d_res) (void)hipFree(sl.d_res);
+        if (sl.h_desc) (void)hipHostFree(sl.h_desc);
+        if (sl.h_res) (void)hipHostFree(sl.h_res);
+        if (sl.ev) (void)hipEventDestroy(sl.ev);
+        if (sl.st) (void)hipStreamDestroy(sl.st);
+    }
+    s->slots.clear();
+    if (s->pool.base) (void)hipFree(s->pool.base);
+    s->pool.base = nullptr;
+}
+
+extern "C" {
+
+int64_t vnp_server_clock_ns(void) { return now_ns(); }
+
+int vnp_server_create(vnp_server **srv, const vnp_server_config *cfg)
+{
+    if (!srv) return -1;
+    *srv = nullptr;
+    if (!cfg || cfg->pool_bytes < 0 || cfg->max_batch < 1 || cfg->max_batch > (1 << 20) || cfg->streams < 1 ||
+        cfg->streams > 16 || cfg->max_wait_us < 0 || cfg->inject_failure_every < 0)
+        return -2;
+    vnp_server *s = new (std::nothrow) vnp_server;
+    if (!s) return (int)hipErrorOutOfMemory;
+    s->cfg = *cfg;
+    hipError_t e = hipGetDevice(&s->device);
+    char *pool = nullptr;
+    if (e == hipSuccess && cfg->pool_bytes > 0) e = hipMalloc(reinterpret_cast<void **>(&pool), (size_t)cfg->pool_bytes);
+    s->pool.init(pool, (uint64_t)cfg->pool_bytes);
+    const size_t cap = (size_t)cfg->max_batch;
+    s->slots.resize((size_t)cfg->streams);
+    for (Slot &sl : s->slots) {
+        if (e != hipSuccess) break;
+        e = hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&sl.d_desc), cap * 24);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&sl.d_res), cap * 12);
+        if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&sl.h_desc), cap * 24, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&sl.h_res), cap * 12, hipHostMallocDefault);
+        if (e == hipSuccess) memset(sl.h_desc, 0, cap * 24);
+    }
+    if (e != hipSuccess) {
+        free_slots(s);
+        delete s;
+        return (int)e;
+    }
+    s->st.pool_bytes = cfg->pool_bytes;
+    s->worker = std::thread([s] { s->worker_loop(); });
+    *srv = s;
+    return 0;
+}
+
+int vnp_server_destroy(vnp_server *s)
+{
+    if (!s) return -1;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->pending.clear();
+    }
+    s->cv_work.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    free_slots(s);
+    delete s;
+    return 0;
+}
+
+int vnp_server_alloc(vnp_server *s, int64_t bytes, void **dptr)
+{
+    if (!s) return -1;
+    if (bytes <= 0) return -2;
+    if (!dptr) return -3;
+    std::lock_guard<std::mutex> lk(s->mu);
+    void *p = s->pool.alloc((uint64_t)bytes);
+    if (!p) return VNP_EAGAIN;
+    *dptr = p;
+    return 0;
+}
+
+int vnp_server_free(vnp_server *s, void *dptr)
+{
+    if (!s) return -1;
+    std::lock_guard<std::mutex> lk(s->mu);
+    return s->pool.release(dptr) ? 0 : -2;
+}
+
+int vnp_server_submit(vnp_server *s, const vnp_request *req, uint64_t *ticket)
+{
+    if (!s) return -1;
+    if (!req) return -2;
+    if (!ticket) return -3;
+    int info = 0;
+    if (req->dtype != VNP_F64 && req->dtype != VNP_F32)
+        info = -1;
+    else if (!(req->p > 0))
+        info = -2;
+    else if (req->n < 0 || req->n > VNP_MAX_N)
+        info = -3;
+    else if (req->n > 0 && !req->x)
+        info = -4;
+    else if (req->incx == 0)
+        info = -5;
+    const int64_t t = now_ns();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        const uint64_t id = s->next_ticket++;
+        Ticket tk{};
+        tk.r.t_submit_ns = t;
+        s->st.submitted += 1;
+        if (info) {
+            tk.r.status = info;
+            tk.r.value = __builtin_nan("");
+            tk.r.t_done_ns = t;
+            tk.done = true;
+            s->st.rejected += 1;
+        } else {
+            s->pending.push_back(Pending{id, *req, t, false});
+        }
+        s->tickets.emplace(id, tk);
+        *ticket = id;
+    }
+    if (info)
+        s->cv_done.notify_all();
+    else
+        s->cv_work.notify_one();
+    return 0;
+}
+
+static int take_result(vnp_server *s, uint64_t ticket, vnp_result *out, std::unique_lock<std::mutex> &lk,
+                       int64_t timeout_us)
+{
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end()) return VNP_ENOTFOUND;
+    if (!it->second.done && timeout_us != 0) {
+        auto ready = [&] {
+            auto j = s->tickets.find(ticket);
+            return j == s->tickets.end() || j->second.done;
+        };
+        if (timeout_us < 0)
+            s->cv_done.wait(lk, ready);
+        else
+            s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready);
+        it = s->tickets.find(ticket);
+        if (it == s->tickets.end()) return VNP_ENOTFOUND;
+    }
+    if (!it->second.done) return VNP_EPENDING;
+    if (out) *out = it->second.r;
+    s->tickets.erase(it);
+    return 0;
+}
+
+int vnp_server_poll(vnp_server *s, uint64_t ticket, vnp_result *out)
+{
+    if (!s) return -1;
+    std::unique_lock<std::mutex> lk(s->mu);
+    return take_result(s, ticket, out, lk, 0);
+}
+
+int vnp_server_wait(vnp_server *s, uint64_t ticket, int64_t timeout_us, vnp_result *out)
+{
+    if (!s) return -1;
+    std::unique_lock<std::mutex> lk(s->mu);
+    return take_result(s, ticket, out, lk, timeout_us);
+}
+
+int vnp_server_get_stats(vnp_server *s, vnp_server_stats *out)
+{
+    if (!s) return -1;
+    if (!out) return -2;
+    std::lock_guard<std::mutex> lk(s->mu);
+    vnp_server_stats r = s->st;
+    r.pool_free_bytes = (int64_t)s->pool.free_bytes;
+    r.pending = (int64_t)s->pending.size();
+    int64_t inflight = 0;
+    for (const Slot &sl : s->slots) inflight += sl.busy ? (int64_t)sl.reqs.size() : 0;
+    r.in_flight = inflight;
+    *out = r;
+    return 0;
+}
+
+}  // extern "C"

@@ -186,6 +186,16 @@ def dev_fill(t, kind="u11", lo=0, hi=0, seed=0, stream=0, i0=0):
     return t
 
 
+def dev_fill_ptr(ptr, n, dtype="f64", kind="u11", lo=0, hi=0, seed=0, stream=0, i0=0, hip_stream=0):
+    """Fill n elements at a raw device address (for buffers not owned by torch)."""
+    lib = _load_dev()
+    kind = KINDS[kind] if isinstance(kind, str) else kind
+    fn = lib.vnpg_dev_fill_d if dtype in ("f64", np.float64) else lib.vnpg_dev_fill_s
+    rc = fn(ptr, n, i0, seed, stream, kind, lo, hi, hip_stream)
+    if rc != 0:
+        raise RuntimeError(f"device fill failed: hip error {rc}")
+
+
 def dev_copy(dst, src, nbytes, blocks=0, stream=0):
     rc = _load_dev().vnpg_dev_copy(dst, src, nbytes, blocks, stream)
     if rc != 0:
@@ -196,6 +206,31 @@ def dev_read(src, nbytes, out, blocks, stream=0):
     rc = _load_dev().vnpg_dev_read(src, nbytes, out, blocks, stream)
     if rc != 0:
         raise RuntimeError(f"read failed: {rc}")
+
+
+LOADGEN_LIB = os.path.join(_HERE, "libvnp_loadgen.so")
+
+
+def run_load(server, arrival_s, reqs):
+    """Open-loop replay of requests (vnp.Request array) at arrival times arrival_s (seconds
+    from start) against a vnp.Server; returns (latency_s, values, status, wall_s)."""
+    import paper_2509_06220_amd as vnp
+
+    lg = ctypes.CDLL(LOADGEN_LIB)
+    lg.vnpg_loadgen.restype = ctypes.c_int
+    lg.vnpg_loadgen.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int64] + [ctypes.c_void_p] * 6
+    L = vnp.lib()
+    fp = lambda f: ctypes.cast(f, ctypes.c_void_p).value  # noqa: E731
+    n = len(arrival_s)
+    arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
+    lat = np.zeros(n)
+    val = np.zeros(n)
+    st = np.zeros(n, dtype=np.int32)
+    wall = ctypes.c_double()
+    lg.vnpg_loadgen(server.handle, fp(L.vnp_server_submit), fp(L.vnp_server_wait), fp(L.vnp_server_clock_ns), n,
+                    arr.ctypes.data, ctypes.addressof(reqs), lat.ctypes.data, val.ctypes.data, st.ctypes.data,
+                    ctypes.addressof(wall))
+    return lat, val, st, wall.value
 
 
 def log_uniform_lengths(count, lo_log2, hi_log2, seed=0, stream=7):
