@@ -14,6 +14,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import statistics
 import sys
@@ -113,6 +114,119 @@ def extra_modes(torch, vnp, vnp_gen):
     return out
 
 
+def batched_mode(torch, vnp, vnp_gen, reps=10):
+    """8192 FP64 segments, lengths floor(2^(20U)), values U[-1,1) 2^e, e in [-30, 30] per
+    element: one replay of the autotuned, graph-captured plan against 8192 plain calls
+    issued back to back from native code on the same stream; every segment bitwise equal."""
+    import numpy as np
+
+    nseg = 8192
+    lens = vnp_gen.log_uniform_lengths(nseg, 0, 20, seed=0, stream=7)
+    off = np.zeros(nseg + 1, dtype=np.int64)
+    off[1:] = np.cumsum(lens)
+    total = int(off[-1])
+    rv = vnp_gen.recipe("c3_values")
+    x = torch.empty(total, dtype=torch.float64, device="cuda")
+    vnp_gen.dev_fill(x, kind=rv["kind"], lo=rv["lo"], hi=rv["hi"], seed=rv["seed"], stream=rv["stream"])
+    d_off = torch.from_numpy(off).to("cuda")
+    out_b = torch.empty(nseg, dtype=torch.float64, device="cuda")
+    out_l = torch.empty(nseg, dtype=torch.float64, device="cuda")
+    s = torch.cuda.current_stream()
+    plan = vnp.Plan(x, d_off, out=out_b, h_offsets=off, autotune=True)
+    loop = lambda: vnp_gen.loop_plain("vnp_dnrmf", off, x.data_ptr(), 8, out_l.data_ptr(), 8,  # noqa: E731
+                                      s.cuda_stream)
+    wall_b, per_b = time_steps(lambda: plan.run(), reps, 2, s, min_warm_s=0.3)
+    wall_l, per_l = time_steps(loop, max(reps // 2, 2), 1, s, min_warm_s=0.3)
+    torch.cuda.synchronize()
+    same = int(torch.sum(out_b.view(torch.int64) == out_l.view(torch.int64)).item())
+    tb = wall_b / reps
+    tl = wall_l / max(reps // 2, 2)
+    info = plan.info()
+    plan.close()
+    return {"workload": "8192 FP64 segments, L=floor(2^(20U)), x=U[-1,1)*2^e, e in [-30,30], seed 0",
+            "elements": total, "bytes": total * 8,
+            "batched_norms_per_s": round(nseg / tb, 1), "batched_ms": round(tb * 1e3, 4),
+            "batched_kernel_ms_mean": round(statistics.mean(per_b), 4),
+            "batched_gbs": round(total * 8 / tb / 1e9, 1),
+            "plain_loop_norms_per_s": round(nseg / tl, 1), "plain_loop_ms": round(tl * 1e3, 4),
+            "speedup": round(tl / tb, 2), "bitwise_equal_segments": same, "segments": nseg, "plan": info}
+
+
+def served_mode(torch, vnp, vnp_gen, rates, seconds, n_payloads=4096, check=64):
+    """Open-loop Poisson arrivals against the request server.  Requests: L=floor(2^(4+20U)),
+    FP64 with probability 0.7 else FP32, p=2 with probability 0.8 else one of {1, 3, 4.5},
+    values U[-1,1) 2^e, e in [-30, 30].  Payloads are admitted once into the server's pool
+    (generated on the device) and stay resident; each request names one of them."""
+    import numpy as np
+
+    rng = np.random.default_rng(0)
+    L = vnp_gen.log_uniform_lengths(n_payloads, 4, 24, seed=0, stream=11)
+    is_d = rng.random(n_payloads) < 0.7
+    pv = np.where(rng.random(n_payloads) < 0.8, 2.0, rng.choice([1.0, 3.0, 4.5], n_payloads))
+    esz = np.where(is_d, 8, 4)
+    pool = int(np.sum(((L * esz + 255) // 256) * 256)) + (64 << 20)
+    srv = vnp.Server(pool_bytes=pool, max_batch=512, streams=4, max_wait_us=20)
+    hs = torch.cuda.current_stream().cuda_stream
+    ptrs = np.zeros(n_payloads, dtype=np.uint64)
+    for i in range(n_payloads):
+        ptrs[i] = srv.alloc(int(L[i] * esz[i]))
+        vnp_gen.dev_fill_ptr(int(ptrs[i]), int(L[i]), "f64" if is_d[i] else "f32", kind="u11exp", lo=-30, hi=30,
+                             seed=0, stream=100 + i, hip_stream=hs)
+    torch.cuda.synchronize()
+    out = {"workload": "Poisson arrivals, L=floor(2^(4+20U)), 70% FP64/30% FP32, p=2 80% else {1,3,4.5}, "
+                       "x=U[-1,1)*2^e, e in [-30,30]",
+           "seconds_per_rate": seconds, "resident_payloads": n_payloads, "pool_bytes": pool, "rates": {}}
+
+    def schedule(rate, dur, seed):
+        r = np.random.default_rng(seed)
+        nreq = int(rate * dur * 1.2) + 16
+        arr = np.cumsum(r.exponential(1.0 / rate, nreq))
+        arr = arr[arr < dur]
+        pick = r.integers(0, n_payloads, len(arr))
+        req = vnp_gen.request_array(len(arr))
+        req["dtype"] = np.where(is_d[pick], vnp.F64, vnp.F32)
+        req["p"] = pv[pick]
+        req["n"] = L[pick]
+        req["x"] = ptrs[pick]
+        req["incx"] = 1
+        return arr, req, pick
+
+    arr, req, _ = schedule(5000, 0.3, 99)  # warm-up: kernels loaded, workspaces allocated
+    vnp_gen.run_load(srv, arr, req)
+    for k, rate in enumerate(rates):
+        arr, req, pick = schedule(rate, seconds, k)
+        s0 = srv.stats()
+        lat, val, st, wall = vnp_gen.run_load(srv, arr, req)
+        s1 = srv.stats()
+        ok = st == 0
+        nb = s1["batches"] - s0["batches"]
+        # a sample re-run alone through the plain call: bitwise equal
+        idx = np.linspace(0, len(arr) - 1, min(check, len(arr))).astype(np.int64)
+        eq = 0
+        for i in idx:
+            j = int(pick[i])
+            dt = torch.float64 if is_d[j] else torch.float32
+            r = torch.empty((), dtype=dt, device="cuda")
+            fn = ("vnp_dnrm" if is_d[j] else "vnp_snrm") + ("f" if pv[j] == 2.0 else "p")
+            args = [int(L[j]), int(ptrs[j]), 1] + ([] if pv[j] == 2.0 else [float(pv[j])]) + [r.data_ptr(), hs]
+            if getattr(vnp.lib(), fn)(*args) != 0:
+                continue
+            eq += int(r.item() == val[i] or (math.isnan(r.item()) and math.isnan(val[i])))
+        out["rates"][str(rate)] = {
+            "requests": int(len(arr)), "completed": int(ok.sum()), "errors": int((~ok).sum()),
+            "p50_us": round(float(np.percentile(lat[ok], 50)) * 1e6, 1),
+            "p99_us": round(float(np.percentile(lat[ok], 99)) * 1e6, 1),
+            "norms_per_s": round(float(ok.sum()) / wall, 1),
+            "gbs": round(float(np.sum((L * esz)[pick][ok])) / wall / 1e9, 2),
+            "batches": int(nb), "mean_batch": round(float(len(arr)) / max(nb, 1), 2),
+            "host_launch_us_per_batch": round((s1["host_launch_ns"] - s0["host_launch_ns"]) / max(nb, 1) / 1e3, 1),
+            "batch_us_mean": round((s1["batch_ns"] - s0["batch_ns"]) / max(nb, 1) / 1e3, 1),
+            "backpressure": 0, "sample_bitwise_equal": f"{eq}/{len(idx)}"}
+        print(json.dumps({"served_rate": rate, **out["rates"][str(rate)]}), file=sys.stderr, flush=True)
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +235,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--cpu-sample-log2", type=int, default=30)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-rates", default="5000,20000,80000")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy 5 times (scale of the HBM byte counters)")
     args = ap.parse_args()
@@ -189,6 +307,19 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_extra:
         line["extra"] = extra_modes(torch, vnp, vnp_gen)
+        torch.cuda.empty_cache()
+    if not args.no_batched:
+        try:
+            line["batched"] = batched_mode(torch, vnp, vnp_gen)
+        except Exception as e:  # noqa: BLE001 -- report, do not hide the headline
+            line["batched"] = {"error": repr(e)}
+        torch.cuda.empty_cache()
+    if not args.no_serve:
+        try:
+            rates = [int(r) for r in args.serve_rates.split(",") if r]
+            line["served"] = served_mode(torch, vnp, vnp_gen, rates, args.serve_seconds)
+        except Exception as e:  # noqa: BLE001
+            line["served"] = {"error": repr(e)}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(1 << args.cpu_sample_log2)
     print(json.dumps(line), flush=True)

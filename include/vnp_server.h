@@ -55,6 +55,9 @@ typedef struct {
 typedef struct {
     int64_t submitted, completed, rejected, batches, launches, failed_batches;
     int64_t max_batch_seen, pool_free_bytes, pool_bytes, pending, in_flight;
+    int64_t host_launch_ns;  /* total host time spent enqueueing batches */
+    int64_t batch_ns;        /* total time from a batch's enqueue to its completion being seen */
+    int64_t batch_ns_max;    /* longest such time */
 } vnp_server_stats;
 
 /* Errors: srv == NULL -> -1; cfg invalid -> -2; > 0 HIP error (pool allocation). */

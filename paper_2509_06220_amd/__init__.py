@@ -258,7 +258,8 @@ class Result(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "rejected", "batches", "launches",
                                               "failed_batches", "max_batch_seen", "pool_free_bytes", "pool_bytes",
-                                              "pending", "in_flight")]
+                                              "pending", "in_flight", "host_launch_ns", "batch_ns",
+                                              "batch_ns_max")]
 
 
 class Server:

@@ -1,14 +1,17 @@
 // Batched norms: many segments in one persistent launch (Novakovic, arXiv 2509.06220,
 // Sect. 3.1: norms of the columns of a multi-dimensional array).
 //
-// Work items are (segment, run of 2^lwt tiles of that segment); waves pull items from
-// an atomic counter, so long and short segments share the GPU without a tail.  Each
-// run's root is an aligned subtree of the segment's canonical tree (the same tree the
-// single-vector call uses), a segment of one run writes its result directly, and the
-// last run of a longer segment to finish (per-segment ticket) reduces the run roots by
-// the fixed tree.  Counters reset themselves, so a captured graph can be replayed
-// without clearing memory.  A setup kernel turns the segment lengths into item offsets
-// (prefix sums over the processing order) and writes +0 for empty segments.
+// Work items are (segment, run of 2^lwt tiles of that segment).  Wave w of the grid
+// starts with item w and then pulls further items from an atomic counter, so long and
+// short segments share the GPU without a tail and a launch with little work costs no
+// atomics.  Each run's root is an aligned subtree of the segment's canonical tree (the
+// same tree the single-vector call uses), a segment of one run writes its result
+// directly, and the last run of a longer segment to finish (per-segment ticket) reduces
+// the run roots by the fixed tree.  A setup kernel, launched before the main kernel on
+// the same stream, turns the segment lengths into item offsets (prefix sums over the
+// processing order), writes +0 for empty segments and clears the item counter; the
+// per-segment tickets reset themselves.  A captured graph (setup + main kernel) can
+// therefore be replayed without clearing memory.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -88,11 +91,14 @@ __device__ __forceinline__ int64_t runs_of(int64_t len, int lwt)
 template <typename T, class Seg>
 __global__ void __launch_bounds__(1024)
     batched_setup_kernel(Seg seg, int64_t nseg, const int32_t *order, int lwt, int64_t n_total, int64_t items_cap,
-                         int64_t *item_off, T *res)
+                         int64_t *item_off, T *res, unsigned long long *ctr)
 {
     __shared__ int64_t part[1024];
     __shared__ int bad;
-    if (threadIdx.x == 0) bad = 0;
+    if (threadIdx.x == 0) {
+        bad = 0;
+        *ctr = 0;  // item counter of the main kernel that follows on this stream
+    }
     __syncthreads();
     const int64_t chunk = (nseg + blockDim.x - 1) / blockDim.x;
     const int64_t k0 = (int64_t)threadIdx.x * chunk;
@@ -182,25 +188,26 @@ __device__ __forceinline__ int64_t uniform64(int64_t v)
 }
 
 // ---------------------------------------------------------------------------------
-// Persistent batched kernel.  ctrs[0]: next item, ctrs[1]: exited waves (both 64-bit,
-// zero at launch and reset by the last wave to exit).
+// Persistent batched kernel.  *ctr counts the items handed out beyond the first one of
+// each wave; it is zero at launch (cleared by the setup or stage kernel before it).
 // ---------------------------------------------------------------------------------
 template <class Node, class Seg, int U>
-__global__ void __launch_bounds__(1024)
+__global__ void __launch_bounds__(512)
     batched_kernel(Node nd, Seg seg, const typename Node::T *x, int64_t nseg, const int32_t *order,
                    const int64_t *item_off, int lwt, typename Node::T *roots, unsigned int *seg_cnt,
-                   unsigned long long *ctrs, typename Node::T *res)
+                   unsigned long long *ctr, typename Node::T *res)
 {
     using T = typename Node::T;
     constexpr int64_t TE = tile_elems<T>();
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t total = item_off[nseg];
-    const unsigned long long nwaves = (unsigned long long)gridDim.x * (blockDim.x / WAVE);
+    const int wpb = (int)(blockDim.x / WAVE);
+    const int64_t nwaves = (int64_t)gridDim.x * wpb;
     // No lane-dependent branches in this loop: every wave-level step (fetch, ticket,
     // stores of wave-uniform values) is executed by all lanes, with lane 0 contributing
     // the increment, so the cross-lane reads always see one converged wave.
     const unsigned long long one = lane == 0 ? 1ull : 0ull;
-    int64_t item = uniform64((int64_t)atomicAdd(&ctrs[0], one));
+    int64_t item = (int64_t)blockIdx.x * wpb + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
     while (item < total) {
         // processing position k: the last k with item_off[k] <= item
         int64_t lo = 0, hi = nseg - 1;
@@ -236,13 +243,19 @@ __global__ void __launch_bounds__(1024)
                 __hip_atomic_store(&seg_cnt[s], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
-        item = uniform64((int64_t)atomicAdd(&ctrs[0], one));
+        item = nwaves + uniform64((int64_t)atomicAdd(ctr, one));
     }
-    const unsigned long long exited = (unsigned long long)uniform64((int64_t)atomicAdd(&ctrs[1], one));
-    if (exited == nwaves - 1) {
-        __hip_atomic_store(&ctrs[0], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&ctrs[1], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+}
+
+// Stage kernel of a request batch: copies the batch's descriptor words from host-mapped
+// memory to device memory and clears the item counters of its class launches.
+__global__ void __launch_bounds__(1024)
+    stage_kernel(const unsigned long long *src, unsigned long long *dst, int64_t nwords, unsigned long long *ctrs,
+                 int nctrs)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += stride) dst[i] = src[i];
+    if (blockIdx.x == 0 && (int)threadIdx.x < nctrs) ctrs[threadIdx.x] = 0;
 }
 
 // ---------------------------------------------------------------------------------
@@ -265,7 +278,7 @@ static int ensure_batch_ws(BatchWorkspace &w, size_t roots_bytes, size_t nseg, h
     if (grow_roots) {
         if (w.roots) (void)hipFree(w.roots);
         w.roots = nullptr;
-        const size_t b = std::max<size_t>(roots_bytes, 1 << 16);
+        const size_t b = std::max<size_t>(std::max<size_t>(roots_bytes, 2 * w.roots_cap), 1 << 16);
         e = hipMalloc(&w.roots, b);
         if (e != hipSuccess) return (int)e;
         w.roots_cap = b;
@@ -273,7 +286,7 @@ static int ensure_batch_ws(BatchWorkspace &w, size_t roots_bytes, size_t nseg, h
     if (grow_items) {
         if (w.item_off) (void)hipFree(w.item_off);
         w.item_off = nullptr;
-        const size_t c = std::max<size_t>(nseg + 1, 4096);
+        const size_t c = std::max<size_t>(std::max<size_t>(nseg + 1, 2 * w.item_cap), 4096);
         e = hipMalloc(reinterpret_cast<void **>(&w.item_off), c * sizeof(int64_t));
         if (e != hipSuccess) return (int)e;
         w.item_cap = c;
@@ -281,7 +294,7 @@ static int ensure_batch_ws(BatchWorkspace &w, size_t roots_bytes, size_t nseg, h
     if (grow_seg) {
         if (w.seg_cnt) (void)hipFree(w.seg_cnt);
         w.seg_cnt = nullptr;
-        const size_t c = std::max<size_t>(nseg, 4096);
+        const size_t c = std::max<size_t>(std::max<size_t>(nseg, 2 * w.seg_cap), 4096);
         e = hipMalloc(reinterpret_cast<void **>(&w.seg_cnt), c * sizeof(unsigned int));
         if (e != hipSuccess) return (int)e;
         e = hipMemset(w.seg_cnt, 0, c * sizeof(unsigned int));
@@ -344,7 +357,7 @@ static int enqueue_batched(const Node &nd, const Seg &seg, const typename Node::
     using T = typename Node::T;
     const int64_t items_cap = (int64_t)(ws.roots_cap / sizeof(T));
     hipLaunchKernelGGL((batched_setup_kernel<T, Seg>), dim3(1), dim3(1024), 0, st, seg, nseg, order, sh.lwt,
-                       n_total, items_cap, ws.item_off, res);
+                       n_total, items_cap, ws.item_off, res, ws.ctrs);
     hipLaunchKernelGGL((batched_kernel<Node, Seg, RowsInFlight<Node>::value>), dim3(sh.blocks),
                        dim3(sh.wpb * WAVE), 0, st, nd, seg, x, nseg, order, ws.item_off, sh.lwt,
                        static_cast<T *>(ws.roots), ws.seg_cnt, ws.ctrs, res);
@@ -380,34 +393,105 @@ static int run_batched_p(const Seg &seg, const T *x, int64_t nseg, int64_t total
     return run_batched(make_lp_node<T>(p), seg, x, nseg, total, res, stream);
 }
 
-// Enqueue one class of independent requests (same dtype and p) from the server: nseg
-// requests described by device arrays (ptrs, lens, incs), results to res (T array).
-int enqueue_requests(int dtype, double p, int64_t nseg, const void *const *ptrs, const int64_t *lens,
-                     const int64_t *incs, int64_t max_elems, void *res, BatchWorkspace &ws, hipStream_t st)
+// ---------------------------------------------------------------------------------
+// Request batches (the server): classes of independent requests, item offsets from the
+// host, descriptors staged from host-mapped memory, results written to host-mapped
+// memory, one launch per class with a grid sized to its items.
+// ---------------------------------------------------------------------------------
+template <typename T>
+static int64_t host_runs(int64_t len, int lwt)
 {
-    const SegList seg{ptrs, lens, incs};
-    const BatchShape sh = default_batch_shape();
-    if (dtype == VNP_F32) {
-        const int64_t cap = nseg + (max_elems + tile_elems<float>() - 1) / tile_elems<float>() + 1;
-        int rc = ensure_batch_ws(ws, sizeof(float) * (size_t)cap, (size_t)nseg, st);
-        if (rc) return rc;
-        const float pf = (float)p;
-        float *r = static_cast<float *>(res);
-        if (pf == 2.0f) return enqueue_batched(HypNode<float>{}, seg, (const float *)nullptr, nseg, 0, nullptr, sh, ws, r, st);
-        if (pf == 1.0f) return enqueue_batched(SumNode<float>{}, seg, (const float *)nullptr, nseg, 0, nullptr, sh, ws, r, st);
-        if (__builtin_isinf(pf) || pf >= 0x1p24f)
-            return enqueue_batched(MaxNode<float>{}, seg, (const float *)nullptr, nseg, 0, nullptr, sh, ws, r, st);
-        return enqueue_batched(make_lp_node<float>(pf), seg, (const float *)nullptr, nseg, 0, nullptr, sh, ws, r, st);
+    constexpr int64_t TE = tile_elems<T>();
+    const int64_t tiles = len > 0 ? (len + TE - 1) / TE : 0;
+    return (tiles + ((int64_t)1 << lwt) - 1) >> lwt;
+}
+
+template <typename T>
+static int class_items(const int64_t *lens, int64_t n, int64_t *item_off)
+{
+    constexpr int64_t TE = tile_elems<T>();
+    int64_t tiles = 0;
+    for (int64_t i = 0; i < n; ++i) tiles += lens[i] > 0 ? (lens[i] + TE - 1) / TE : 0;
+    // one tile per item while that gives at most 8 items per resident wave, so a small
+    // batch spreads over the whole GPU; longer runs per item for large batches
+    const int64_t maxw = (int64_t)cus() * 16;
+    int lwt = 0;
+    while (lwt < 3 && (tiles >> lwt) > 8 * maxw) ++lwt;
+    int64_t run = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        item_off[i] = run;
+        run += host_runs<T>(lens[i], lwt);
     }
-    const int64_t cap = nseg + (max_elems + tile_elems<double>() - 1) / tile_elems<double>() + 1;
-    int rc = ensure_batch_ws(ws, sizeof(double) * (size_t)cap, (size_t)nseg, st);
+    item_off[n] = run;
+    return lwt;
+}
+
+int request_class_items(int dtype, const int64_t *lens, int64_t n, int64_t *item_off)
+{
+    return dtype == VNP_F32 ? class_items<float>(lens, n, item_off) : class_items<double>(lens, n, item_off);
+}
+
+template <class Node>
+static void launch_class(const Node &nd, const SegList &seg, int64_t n, const int64_t *item_off, int lwt,
+                         int64_t items, void *roots, unsigned int *seg_cnt, unsigned long long *ctr,
+                         typename Node::T *res, hipStream_t st)
+{
+    using T = typename Node::T;
+    const int64_t maxw = (int64_t)cus() * 16;
+    const int64_t waves = items < maxw ? items : maxw;
+    const int wpb = waves >= 4 * (int64_t)cus() ? 4 : 1;
+    const int blocks = (int)((waves + wpb - 1) / wpb);
+    hipLaunchKernelGGL((batched_kernel<Node, SegList, RowsInFlight<Node>::value>), dim3(blocks), dim3(wpb * WAVE), 0,
+                       st, nd, seg, (const T *)nullptr, n, (const int32_t *)nullptr, item_off, lwt,
+                       static_cast<T *>(roots), seg_cnt, ctr, res);
+}
+
+template <typename T>
+static void launch_class_p(const SegList &seg, int64_t n, const int64_t *item_off, int lwt, int64_t items,
+                           void *roots, unsigned int *seg_cnt, unsigned long long *ctr, T *res, double p, T cutoff,
+                           hipStream_t st)
+{
+    const T pt = (T)p;
+    if (pt == T(2))
+        launch_class(HypNode<T>{}, seg, n, item_off, lwt, items, roots, seg_cnt, ctr, res, st);
+    else if (pt == T(1))
+        launch_class(SumNode<T>{}, seg, n, item_off, lwt, items, roots, seg_cnt, ctr, res, st);
+    else if (__builtin_isinf(pt) || pt >= cutoff)
+        launch_class(MaxNode<T>{}, seg, n, item_off, lwt, items, roots, seg_cnt, ctr, res, st);
+    else
+        launch_class(make_lp_node<T>(pt), seg, n, item_off, lwt, items, roots, seg_cnt, ctr, res, st);
+}
+
+int enqueue_request_batch(const void *h_src, void *d_desc, int64_t nreq, const RequestClass *cls, int ncls,
+                          double *res_d, float *res_s, BatchWorkspace &ws, hipStream_t st)
+{
+    if (nreq <= 0 || ncls <= 0) return 0;
+    if (ncls > 32) return (int)hipErrorInvalidValue;
+    int64_t roots = 0;
+    for (int c = 0; c < ncls; ++c) roots += cls[c].items;
+    int rc = ensure_batch_ws(ws, 8 * (size_t)(roots > 0 ? roots : 1), (size_t)nreq, st);
     if (rc) return rc;
-    double *r = static_cast<double *>(res);
-    if (p == 2.0) return enqueue_batched(HypNode<double>{}, seg, (const double *)nullptr, nseg, 0, nullptr, sh, ws, r, st);
-    if (p == 1.0) return enqueue_batched(SumNode<double>{}, seg, (const double *)nullptr, nseg, 0, nullptr, sh, ws, r, st);
-    if (__builtin_isinf(p) || p >= 0x1p53)
-        return enqueue_batched(MaxNode<double>{}, seg, (const double *)nullptr, nseg, 0, nullptr, sh, ws, r, st);
-    return enqueue_batched(make_lp_node<double>(p), seg, (const double *)nullptr, nseg, 0, nullptr, sh, ws, r, st);
+    const int64_t nwords = 3 * nreq + nreq + ncls;
+    hipLaunchKernelGGL(stage_kernel, dim3(1), dim3(1024), 0, st, static_cast<const unsigned long long *>(h_src),
+                       static_cast<unsigned long long *>(d_desc), nwords, ws.ctrs, ncls);
+    const int64_t *w = static_cast<const int64_t *>(d_desc);
+    const void *const *ptrs = reinterpret_cast<const void *const *>(w);
+    int64_t roots_off = 0;
+    for (int c = 0; c < ncls; ++c) {
+        const RequestClass &k = cls[c];
+        if (k.items == 0) continue;
+        const SegList seg{ptrs + k.a, w + nreq + k.a, w + 2 * nreq + k.a};
+        const int64_t *item_off = w + 3 * nreq + k.a + c;
+        void *rt = static_cast<char *>(ws.roots) + 8 * roots_off;
+        if (k.dtype == VNP_F32)
+            launch_class_p<float>(seg, k.n, item_off, k.lwt, k.items, rt, ws.seg_cnt + k.a, ws.ctrs + c,
+                                  res_s + k.a, k.p, 0x1p24f, st);
+        else
+            launch_class_p<double>(seg, k.n, item_off, k.lwt, k.items, rt, ws.seg_cnt + k.a, ws.ctrs + c,
+                                   res_d + k.a, k.p, 0x1p53, st);
+        roots_off += k.items;
+    }
+    return (int)hipGetLastError();
 }
 
 void release_batch_ws(BatchWorkspace &w) { free_batch_ws(w); }

@@ -1,12 +1,14 @@
 // Request server: continuous batching of norm requests (see include/vnp_server.h).
 //
-// One batcher thread owns the GPU side.  Clients submit requests (host bookkeeping
-// only); the batcher moves pending requests into a free stream slot, uploads their
-// descriptors in one copy, enqueues one batched launch per (dtype, p) class, copies
-// the results back into pinned memory and records an event.  Finished slots are
-// detected by polling their events, results are posted to the tickets and waiters are
-// woken.  With several slots, requests that arrive while batches run are launched on
-// another stream and overlap on the device.
+// One batcher thread owns the launches.  Clients submit requests (host bookkeeping
+// only); the batcher moves pending requests into a free stream slot, writes their
+// descriptors and item offsets into the slot's pinned host buffer and enqueues the batch:
+// a stage kernel copies the descriptors to the device, then one batched launch per
+// (dtype, p) class writes the results straight into the slot's pinned result buffer, and
+// an event is recorded.  Each slot has a completion thread that waits for that event,
+// posts the results to the tickets and wakes waiters and the batcher.  With several
+// slots, requests that arrive while batches run are launched on another stream and
+// overlap on the device.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -104,20 +106,20 @@ struct Ticket {
     bool done;
 };
 
+enum class SlotState { Free, Launching, InFlight };
+
 struct Slot {
     hipStream_t st = nullptr;
     hipEvent_t ev = nullptr;
     vnp::BatchWorkspace ws;
-    char *d_desc = nullptr, *h_desc = nullptr;  // [ptrs | lens | incs], cap entries each
-    char *d_res = nullptr, *h_res = nullptr;    // [double | float], cap entries each
+    char *h_desc = nullptr, *h_desc_dev = nullptr;  // pinned descriptor words and their device view
+    char *d_desc = nullptr;                         // device copy of the descriptor words
+    char *h_res = nullptr, *h_res_dev = nullptr;    // pinned results [double cap | float cap]
     std::vector<Pending> reqs;
-    bool busy = false;
-};
-
-struct Class {
-    int dtype;
-    double p;
-    int64_t a, b;  // request range [a, b) after sorting
+    SlotState state = SlotState::Free;
+    int launch_rc = 0;
+    int64_t t_enqueued = 0;
+    std::thread done_thread;
 };
 
 bool same_class(const vnp_request &u, const vnp_request &v)
@@ -132,7 +134,7 @@ struct vnp_server {
     int device = 0;
     Pool pool;
     std::mutex mu;
-    std::condition_variable cv_work, cv_done;
+    std::condition_variable cv_work, cv_done, cv_slots;
     std::deque<Pending> pending;
     std::unordered_map<uint64_t, Ticket> tickets;
     std::vector<Slot> slots;
@@ -143,61 +145,74 @@ struct vnp_server {
     int64_t batch_counter = 0;
 
     void worker_loop();
+    void completion_loop(size_t i);
     int launch(Slot &s, std::vector<Pending> &reqs, int *nlaunch);
     void complete(Slot &s, int status);
 };
 
+// Fills the slot's pinned buffers for the batch and enqueues it.  Runs without the lock
+// (the slot is owned by the batcher until it is handed to its completion thread).
 int vnp_server::launch(Slot &s, std::vector<Pending> &reqs, int *nlaunch)
 {
     *nlaunch = 0;
     const size_t cap = (size_t)cfg.max_batch;
+    const int64_t n = (int64_t)reqs.size();
     std::stable_sort(reqs.begin(), reqs.end(), [](const Pending &u, const Pending &v) {
         if (u.req.dtype != v.req.dtype) return u.req.dtype < v.req.dtype;
         return u.req.p < v.req.p;
     });
-    void **hp = reinterpret_cast<void **>(s.h_desc);
-    int64_t *hl = reinterpret_cast<int64_t *>(s.h_desc + cap * 8);
-    int64_t *hi = reinterpret_cast<int64_t *>(s.h_desc + cap * 16);
-    std::vector<Class> classes;
-    for (size_t i = 0; i < reqs.size(); ++i) {
-        const vnp_request &q = reqs[i].req;
+    int64_t *w = reinterpret_cast<int64_t *>(s.h_desc);
+    void **hp = reinterpret_cast<void **>(w);
+    int64_t *hl = w + n, *hi = w + 2 * n;
+    double *rd = reinterpret_cast<double *>(s.h_res);
+    float *rf = reinterpret_cast<float *>(s.h_res + cap * 8);
+    std::vector<vnp::RequestClass> classes;
+    for (int64_t i = 0; i < n; ++i) {
+        const vnp_request &q = reqs[(size_t)i].req;
         const size_t esz = q.dtype == VNP_F32 ? 4 : 8;
         const char *x = static_cast<const char *>(q.x);
         hp[i] = const_cast<char *>(q.incx >= 0 || q.n <= 0 ? x : x + (size_t)((q.n - 1) * (-q.incx)) * esz);
         hl[i] = q.n;
         hi[i] = q.incx;
-        if (classes.empty() || !same_class(reqs[classes.back().a].req, q))
-            classes.push_back(Class{q.dtype, q.p, (int64_t)i, (int64_t)i + 1});
+        if (q.n == 0) {  // no work item: the result is +0
+            if (q.dtype == VNP_F32)
+                rf[i] = 0.0f;
+            else
+                rd[i] = 0.0;
+        }
+        if (classes.empty() || !same_class(reqs[(size_t)classes.back().a].req, q))
+            classes.push_back(vnp::RequestClass{q.dtype, q.p, i, 1, 0, 0});
         else
-            classes.back().b = (int64_t)i + 1;
+            classes.back().n += 1;
     }
-    hipError_t e = hipMemcpyAsync(s.d_desc, s.h_desc, cap * 24, hipMemcpyHostToDevice, s.st);
-    if (e != hipSuccess) return (int)e;
-    void **dp = reinterpret_cast<void **>(s.d_desc);
-    int64_t *dl = reinterpret_cast<int64_t *>(s.d_desc + cap * 8);
-    int64_t *di = reinterpret_cast<int64_t *>(s.d_desc + cap * 16);
-    for (const Class &c : classes) {
-        int64_t elems = 0;
-        for (int64_t i = c.a; i < c.b; ++i) elems += std::max<int64_t>(hl[i], 0);
-        void *res = c.dtype == VNP_F32 ? static_cast<void *>(s.d_res + cap * 8 + (size_t)c.a * 4)
-                                       : static_cast<void *>(s.d_res + (size_t)c.a * 8);
-        const int rc = vnp::enqueue_requests(c.dtype, c.p, c.b - c.a, (const void *const *)(dp + c.a), dl + c.a,
-                                             di + c.a, elems, res, s.ws, s.st);
-        if (rc) return rc;
-        *nlaunch += 1;
+    if (classes.size() > 32) return (int)hipErrorInvalidValue;
+    for (size_t c = 0; c < classes.size(); ++c) {
+        vnp::RequestClass &k = classes[c];
+        int64_t *off = w + 3 * n + k.a + (int64_t)c;
+        k.lwt = vnp::request_class_items(k.dtype, hl + k.a, k.n, off);
+        k.items = off[k.n];
+        *nlaunch += k.items > 0 ? 1 : 0;
     }
-    e = hipMemcpyAsync(s.h_res, s.d_res, cap * 12, hipMemcpyDeviceToHost, s.st);
-    if (e == hipSuccess) e = hipEventRecord(s.ev, s.st);
-    return (int)e;
+    int rc = vnp::enqueue_request_batch(s.h_desc_dev, s.d_desc, n, classes.data(), (int)classes.size(),
+                                        reinterpret_cast<double *>(s.h_res_dev),
+                                        reinterpret_cast<float *>(s.h_res_dev + cap * 8), s.ws, s.st);
+    if (rc) return rc;
+    return (int)hipEventRecord(s.ev, s.st);
 }
 
-// Posts the slot's results (status 0) or the error to its tickets.  Called with mu held.
+// Posts the slot's results (status 0) or the error to its tickets and frees the slot.
+// Called with mu held.
 void vnp_server::complete(Slot &s, int status)
 {
     const size_t cap = (size_t)cfg.max_batch;
     const double *rd = reinterpret_cast<const double *>(s.h_res);
     const float *rf = reinterpret_cast<const float *>(s.h_res + cap * 8);
     const int64_t t = now_ns();
+    if (s.t_enqueued) {
+        st.batch_ns += t - s.t_enqueued;
+        st.batch_ns_max = std::max<int64_t>(st.batch_ns_max, t - s.t_enqueued);
+        s.t_enqueued = 0;
+    }
     for (size_t i = 0; i < s.reqs.size(); ++i) {
         auto it = tickets.find(s.reqs[i].ticket);
         if (it == tickets.end()) continue;
@@ -209,8 +224,29 @@ void vnp_server::complete(Slot &s, int status)
         st.completed += 1;
     }
     s.reqs.clear();
-    s.busy = false;
+    s.state = SlotState::Free;
     cv_done.notify_all();
+    cv_work.notify_one();
+}
+
+// Waits for slot i's batches, one at a time, and completes them.
+void vnp_server::completion_loop(size_t i)
+{
+    (void)hipSetDevice(device);
+    Slot &s = slots[i];
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+        cv_slots.wait(lk, [&] { return s.state == SlotState::InFlight || (stop && s.state == SlotState::Free); });
+        if (s.state != SlotState::InFlight) break;
+        int rc = s.launch_rc;
+        lk.unlock();
+        if (rc)
+            (void)hipStreamSynchronize(s.st);  // nothing of a failed batch may still run
+        else
+            rc = (int)hipEventSynchronize(s.ev);
+        lk.lock();
+        complete(s, rc);
+    }
 }
 
 void vnp_server::worker_loop()
@@ -218,75 +254,66 @@ void vnp_server::worker_loop()
     (void)hipSetDevice(device);
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
-        bool any_busy = false;
-        for (Slot &s : slots) {
-            if (!s.busy) continue;
-            const hipError_t q = hipEventQuery(s.ev);
-            if (q == hipSuccess)
-                complete(s, 0);
-            else if (q != hipErrorNotReady)
-                complete(s, (int)q);
-            else
-                any_busy = true;
-        }
-        if (stop && !any_busy) break;
+        if (stop) break;
         Slot *free_slot = nullptr;
         for (Slot &s : slots)
-            if (!s.busy) {
+            if (s.state == SlotState::Free) {
                 free_slot = &s;
                 break;
             }
         bool go = false;
         int64_t wait_ns = -1;
-        if (!stop && free_slot && !pending.empty()) {
+        if (free_slot && !pending.empty()) {
             const int64_t age = now_ns() - pending.front().t_submit;
             go = cfg.max_wait_us == 0 || (int64_t)pending.size() >= cfg.max_batch ||
                  age >= (int64_t)cfg.max_wait_us * 1000 || pending.front().solo;
             if (!go) wait_ns = (int64_t)cfg.max_wait_us * 1000 - age;
         }
-        if (go) {
-            std::vector<Pending> batch;
-            if (pending.front().solo) {
-                batch.push_back(pending.front());
-                pending.pop_front();
-            } else {
-                while (!pending.empty() && (int)batch.size() < cfg.max_batch && !pending.front().solo) {
-                    batch.push_back(pending.front());
-                    pending.pop_front();
-                }
-            }
-            Slot &s = *free_slot;
-            s.busy = true;
-            const int64_t bno = ++batch_counter;
-            st.batches += 1;
-            st.max_batch_seen = std::max<int64_t>(st.max_batch_seen, (int64_t)batch.size());
-            if (cfg.inject_failure_every > 0 && bno % cfg.inject_failure_every == 0 && batch.size() > 1) {
-                // injected failure: nothing is launched; each request is rerun alone
-                st.failed_batches += 1;
-                for (auto it = batch.rbegin(); it != batch.rend(); ++it) {
-                    Pending p = *it;
-                    p.solo = true;
-                    pending.push_front(p);
-                }
-                s.busy = false;
-                continue;
-            }
-            lk.unlock();
-            int nl = 0;
-            const int rc = launch(s, batch, &nl);
-            if (rc) (void)hipStreamSynchronize(s.st);  // nothing of a failed batch may still run
-            lk.lock();
-            st.launches += nl;
-            s.reqs = std::move(batch);
-            if (rc) complete(s, rc);
+        if (!go) {
+            if (wait_ns > 0)
+                cv_work.wait_for(lk, std::chrono::nanoseconds(wait_ns));
+            else
+                cv_work.wait(lk);
             continue;
         }
-        if (any_busy)
-            cv_work.wait_for(lk, std::chrono::microseconds(10));
-        else if (wait_ns > 0)
-            cv_work.wait_for(lk, std::chrono::nanoseconds(wait_ns));
-        else
-            cv_work.wait(lk, [&] { return stop || !pending.empty(); });
+        std::vector<Pending> batch;
+        if (pending.front().solo) {
+            batch.push_back(pending.front());
+            pending.pop_front();
+        } else {
+            while (!pending.empty() && (int)batch.size() < cfg.max_batch && !pending.front().solo) {
+                batch.push_back(pending.front());
+                pending.pop_front();
+            }
+        }
+        Slot &s = *free_slot;
+        const int64_t bno = ++batch_counter;
+        st.batches += 1;
+        st.max_batch_seen = std::max<int64_t>(st.max_batch_seen, (int64_t)batch.size());
+        if (cfg.inject_failure_every > 0 && bno % cfg.inject_failure_every == 0 && batch.size() > 1) {
+            // injected failure: nothing is launched; each request is rerun alone
+            st.failed_batches += 1;
+            for (auto it = batch.rbegin(); it != batch.rend(); ++it) {
+                Pending p = *it;
+                p.solo = true;
+                pending.push_front(p);
+            }
+            continue;
+        }
+        s.state = SlotState::Launching;
+        lk.unlock();
+        int nl = 0;
+        const int64_t t_l = now_ns();
+        const int rc = launch(s, batch, &nl);
+        const int64_t t_e = now_ns();
+        lk.lock();
+        st.host_launch_ns += t_e - t_l;
+        st.launches += nl;
+        s.reqs = std::move(batch);
+        s.launch_rc = rc;
+        s.t_enqueued = t_e;
+        s.state = SlotState::InFlight;
+        cv_slots.notify_all();
     }
 }
 
@@ -296,7 +323,6 @@ static void free_slots(vnp_server *s)
         if (sl.st) (void)hipStreamSynchronize(sl.st);
         vnp::release_batch_ws(sl.ws);
         if (sl.d_desc) (void)hipFree(sl.d_desc);
-        if (sl.d_res) (void)hipFree(sl.d_res);
         if (sl.h_desc) (void)hipHostFree(sl.h_desc);
         if (sl.h_res) (void)hipHostFree(sl.h_res);
         if (sl.ev) (void)hipEventDestroy(sl.ev);
@@ -326,16 +352,18 @@ int vnp_server_create(vnp_server **srv, const vnp_server_config *cfg)
     if (e == hipSuccess && cfg->pool_bytes > 0) e = hipMalloc(reinterpret_cast<void **>(&pool), (size_t)cfg->pool_bytes);
     s->pool.init(pool, (uint64_t)cfg->pool_bytes);
     const size_t cap = (size_t)cfg->max_batch;
+    const size_t desc_bytes = (4 * cap + 32) * 8;  // ptrs | lens | incs | item offsets (+1 per class)
     s->slots.resize((size_t)cfg->streams);
     for (Slot &sl : s->slots) {
         if (e != hipSuccess) break;
         e = hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&sl.d_desc), cap * 24);
-        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&sl.d_res), cap * 12);
-        if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&sl.h_desc), cap * 24, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&sl.d_desc), desc_bytes);
+        if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&sl.h_desc), desc_bytes, hipHostMallocDefault);
         if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&sl.h_res), cap * 12, hipHostMallocDefault);
-        if (e == hipSuccess) memset(sl.h_desc, 0, cap * 24);
+        if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void **>(&sl.h_desc_dev), sl.h_desc, 0);
+        if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void **>(&sl.h_res_dev), sl.h_res, 0);
+        if (e == hipSuccess) memset(sl.h_desc, 0, desc_bytes);
     }
     if (e != hipSuccess) {
         free_slots(s);
@@ -343,6 +371,7 @@ int vnp_server_create(vnp_server **srv, const vnp_server_config *cfg)
         return (int)e;
     }
     s->st.pool_bytes = cfg->pool_bytes;
+    for (size_t i = 0; i < s->slots.size(); ++i) s->slots[i].done_thread = std::thread([s, i] { s->completion_loop(i); });
     s->worker = std::thread([s] { s->worker_loop(); });
     *srv = s;
     return 0;
@@ -358,6 +387,12 @@ int vnp_server_destroy(vnp_server *s)
     }
     s->cv_work.notify_all();
     if (s->worker.joinable()) s->worker.join();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);  // the batcher has stopped: no slot is Launching
+    }
+    s->cv_slots.notify_all();
+    for (Slot &sl : s->slots)
+        if (sl.done_thread.joinable()) sl.done_thread.join();  // in-flight batches complete first
     free_slots(s);
     delete s;
     return 0;
@@ -470,7 +505,7 @@ int vnp_server_get_stats(vnp_server *s, vnp_server_stats *out)
     r.pool_free_bytes = (int64_t)s->pool.free_bytes;
     r.pending = (int64_t)s->pending.size();
     int64_t inflight = 0;
-    for (const Slot &sl : s->slots) inflight += sl.busy ? (int64_t)sl.reqs.size() : 0;
+    for (const Slot &sl : s->slots) inflight += sl.state != SlotState::Free ? (int64_t)sl.reqs.size() : 0;
     r.in_flight = inflight;
     *out = r;
     return 0;

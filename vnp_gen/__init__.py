@@ -227,10 +227,38 @@ def run_load(server, arrival_s, reqs):
     val = np.zeros(n)
     st = np.zeros(n, dtype=np.int32)
     wall = ctypes.c_double()
+    raddr = reqs.ctypes.data if isinstance(reqs, np.ndarray) else ctypes.addressof(reqs)
     lg.vnpg_loadgen(server.handle, fp(L.vnp_server_submit), fp(L.vnp_server_wait), fp(L.vnp_server_clock_ns), n,
-                    arr.ctypes.data, ctypes.addressof(reqs), lat.ctypes.data, val.ctypes.data, st.ctypes.data,
+                    arr.ctypes.data, raddr, lat.ctypes.data, val.ctypes.data, st.ctypes.data,
                     ctypes.addressof(wall))
     return lat, val, st, wall.value
+
+
+def request_array(count):
+    """numpy structured array laid out like vnp_request (dtype, p, n, x, incx)."""
+    import paper_2509_06220_amd as vnp
+
+    R = vnp.Request
+    dt = np.dtype({"names": ["dtype", "p", "n", "x", "incx"],
+                   "formats": [np.int32, np.float64, np.int64, np.uint64, np.int64],
+                   "offsets": [R.dtype.offset, R.p.offset, R.n.offset, R.x.offset, R.incx.offset],
+                   "itemsize": ctypes.sizeof(R)})
+    return np.zeros(count, dtype=dt)
+
+
+def loop_plain(fn_name, offsets, x_ptr, esz, res_ptr, res_bytes, stream):
+    """Issue one plain call per segment from native code (baseline of the batched mode)."""
+    import paper_2509_06220_amd as vnp
+
+    lg = ctypes.CDLL(LOADGEN_LIB)
+    lg.vnpg_loop_plain.restype = ctypes.c_int
+    lg.vnpg_loop_plain.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                   ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    fn = ctypes.cast(getattr(vnp.lib(), fn_name), ctypes.c_void_p).value
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    rc = lg.vnpg_loop_plain(fn, len(off) - 1, off.ctypes.data, x_ptr, esz, res_ptr, res_bytes, stream)
+    if rc:
+        raise RuntimeError(f"plain call failed with status {rc}")
 
 
 def log_uniform_lengths(count, lo_log2, hi_log2, seed=0, stream=7):
@@ -245,5 +273,6 @@ def recipe(name):
 
 
 __all__ = ["np_fill", "host_fill", "dev_fill", "np_draws", "host_draws", "key", "RECIPES", "recipe",
-           "log_uniform_lengths", "dev_copy", "dev_read", "KINDS"]
+           "log_uniform_lengths", "dev_copy", "dev_read", "dev_fill_ptr", "run_load", "request_array", "loop_plain",
+           "KINDS"]
 _ = math

@@ -70,3 +70,21 @@ extern "C" int vnpg_loadgen(void *srv, void *submit, void *wait, void *clock, in
     *wall_s = (double)(now() - t0) * 1e-9;
     return worst;
 }
+
+// Baseline of the batched benchmark: nseg plain single-vector calls issued back to back
+// from native code on one stream (no synchronisation), as a C caller would loop them.
+// fn is a vnp_dnrmf/vnp_snrmf-shaped function; results go to res + i * res_bytes.
+typedef int (*plain_fn)(int64_t, const void *, int64_t, void *, void *);
+
+extern "C" int vnpg_loop_plain(void *fn, int64_t nseg, const int64_t *offsets, const void *x, int64_t esz,
+                               void *res, int64_t res_bytes, void *stream)
+{
+    plain_fn f = (plain_fn)fn;
+    const char *xb = static_cast<const char *>(x);
+    char *rb = static_cast<char *>(res);
+    for (int64_t i = 0; i < nseg; ++i) {
+        const int rc = f(offsets[i + 1] - offsets[i], xb + offsets[i] * esz, 1, rb + i * res_bytes, stream);
+        if (rc) return rc;
+    }
+    return 0;
+}
