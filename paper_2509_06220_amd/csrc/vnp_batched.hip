@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "../../include/vnp.h"
+#include "vnp_batch.hpp"
 #include "vnp_internal.hpp"
 #include "vnp_nodes_p.hpp"
 
@@ -37,6 +38,7 @@ namespace vnp {
 // element 0), inc(s) (the stride between logical elements) and ok(s, n_total) (the
 // segment lies inside the buffer the caller declared).
 struct SegOffsets {  // segment s = x[off[s] .. off[s+1])
+    static constexpr bool contiguous = true;  // unit stride, element-aligned when x is
     const int64_t *off;
     __device__ int64_t len(int64_t s) const
     {
@@ -54,6 +56,7 @@ struct SegOffsets {  // segment s = x[off[s] .. off[s+1])
 };
 
 struct SegCols {  // column s of a column-major matrix: x[s * lda .. s * lda + m)
+    static constexpr bool contiguous = true;
     int64_t lda, m;
     __device__ int64_t len(int64_t) const { return m; }
     template <typename T>
@@ -63,6 +66,7 @@ struct SegCols {  // column s of a column-major matrix: x[s * lda .. s * lda + m
 };
 
 struct SegList {  // independent requests: len[s] elements at ptr[s] with stride inc[s]
+    static constexpr bool contiguous = false;
     const void *const *ptr;  // address of logical element 0 (already moved for inc < 0)
     const int64_t *lens;
     const int64_t *incs;
@@ -135,51 +139,6 @@ __global__ void __launch_bounds__(1024)
     }
 }
 
-// Tree over r[0..cnt) (zero-padded to a power of two) by one wave; every lane gets the
-// root.  Chunks of 512 (8 per lane, then the lanes) are aligned subtrees, combined by a
-// wave-uniform binary counter.
-template <class Node>
-__device__ typename Node::T wave_finish(const Node &nd, const typename Node::T *r, int64_t cnt, int lane)
-{
-    using T = typename Node::T;
-    T stk[MAX_LWT + 1];
-    const int64_t nck = (cnt + 511) / 512;
-    for (int64_t ck = 0; ck < nck; ++ck) {
-        const int64_t b0 = ck * 512 + lane * 8;
-        T e[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const bool in = b0 + j < cnt;  // branch-free (see LoadGeneric)
-            const T v = r[in ? b0 + j : 0];
-            e[j] = in ? v : T(0);
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) e[j] = nd.node(e[2 * j], e[2 * j + 1]);
-        e[0] = nd.node(e[0], e[1]);
-        e[2] = nd.node(e[2], e[3]);
-        T t = uniform(lane_tree(nd, nd.node(e[0], e[2]), lane));
-        const int idx = (int)ck;
-        bool carry = true;
-#pragma unroll
-        for (int l = 0; l < MAX_LWT; ++l) {
-            const bool bit = (idx >> l) & 1;
-            if (carry && bit) t = uniform(nd.node(stk[l], t));
-            if (carry && !bit) stk[l] = t;
-            carry = carry && bit;
-        }
-    }
-    T cur = T(0);
-    bool any = false;
-#pragma unroll
-    for (int l = 0; l < MAX_LWT; ++l) {
-        if ((nck >> l) & 1) {
-            cur = any ? uniform(nd.node(stk[l], cur)) : stk[l];
-            any = true;
-        }
-    }
-    return cur;
-}
-
 __device__ __forceinline__ int64_t uniform64(int64_t v)
 {
     const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffff));
@@ -187,11 +146,51 @@ __device__ __forceinline__ int64_t uniform64(int64_t v)
     return ((int64_t)hi << 32) | (uint32_t)lo;
 }
 
+// Tree over r[0..cnt) (zero-padded to a power of two) by one wave; every lane gets the
+// root.  Each pass reduces aligned chunks of 512 (8 per lane, then the lanes) to their
+// roots and writes chunk k's root to r[k] (r[k] lies in or before chunk k, whose values
+// are already read), until one value is left; with node(a, 0) = a the passes give the
+// same value as one perfect tree over the zero-padded r.  r is overwritten.
+template <class Node>
+__device__ typename Node::T wave_finish(const Node &nd, typename Node::T *r, int64_t cnt, int lane)
+{
+    using T = typename Node::T;
+    cnt = uniform64(cnt);
+    while (cnt > 1) {
+        const int64_t nck = (cnt + 511) / 512;
+        for (int64_t ck = 0; ck < nck; ++ck) {
+            const int64_t b0 = ck * 512 + lane * 8;
+            T e[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const bool in = b0 + j < cnt;  // branch-free (see LoadGeneric)
+                const T v = r[in ? b0 + j : 0];
+                e[j] = in ? v : T(0);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) e[j] = nd.node(e[2 * j], e[2 * j + 1]);
+            e[0] = nd.node(e[0], e[1]);
+            e[2] = nd.node(e[2], e[3]);
+            const T t = uniform(lane_tree(nd, nd.node(e[0], e[2]), lane));
+            // all lanes have read chunk ck (the cross-lane steps above need every lane's
+            // value); every lane stores the same root
+            r[ck] = t;
+        }
+        cnt = nck;
+        // the wave's stores are visible to its own loads of the next pass
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    return uniform(r[0]);
+}
+
 // ---------------------------------------------------------------------------------
 // Persistent batched kernel.  *ctr counts the items handed out beyond the first one of
 // each wave; it is zero at launch (cleared by the setup or stage kernel before it).
 // ---------------------------------------------------------------------------------
-template <class Node, class Seg, int U>
+// GEN: segments may be strided or not element-aligned (the generic loader is compiled
+// in); without it every segment takes the vector-load path, which needs fewer registers.
+template <class Node, class Seg, int U, bool GEN>
 __global__ void __launch_bounds__(512)
     batched_kernel(Node nd, Seg seg, const typename Node::T *x, int64_t nseg, const int32_t *order,
                    const int64_t *item_off, int lwt, typename Node::T *roots, unsigned int *seg_cnt,
@@ -226,10 +225,14 @@ __global__ void __launch_bounds__(512)
         const int64_t nruns = (ntiles + ((int64_t)1 << lwt) - 1) >> lwt;
         const T *xs = seg.base(x, s);
         T root;
-        if (inc == 1 && (((uintptr_t)xs) & 15) == 0)
+        if constexpr (GEN) {
+            if (inc == 1 && (((uintptr_t)xs) % sizeof(T)) == 0)
+                root = wave_root<Node, U, true>(nd, xs, len, 1, r << lwt, ntiles, lwt, lane);
+            else
+                root = wave_root<Node, U, false>(nd, xs, len, inc, r << lwt, ntiles, lwt, lane);
+        } else {
             root = wave_root<Node, U, true>(nd, xs, len, 1, r << lwt, ntiles, lwt, lane);
-        else
-            root = wave_root<Node, U, false>(nd, xs, len, inc, r << lwt, ntiles, lwt, lane);
+        }
         if (nruns == 1) {
             res[s] = nd.finish(root);  // every lane stores the same value
         } else {
@@ -358,9 +361,14 @@ static int enqueue_batched(const Node &nd, const Seg &seg, const typename Node::
     const int64_t items_cap = (int64_t)(ws.roots_cap / sizeof(T));
     hipLaunchKernelGGL((batched_setup_kernel<T, Seg>), dim3(1), dim3(1024), 0, st, seg, nseg, order, sh.lwt,
                        n_total, items_cap, ws.item_off, res, ws.ctrs);
-    hipLaunchKernelGGL((batched_kernel<Node, Seg, RowsInFlight<Node>::value>), dim3(sh.blocks),
-                       dim3(sh.wpb * WAVE), 0, st, nd, seg, x, nseg, order, ws.item_off, sh.lwt,
-                       static_cast<T *>(ws.roots), ws.seg_cnt, ws.ctrs, res);
+    if (Seg::contiguous && ((uintptr_t)x % sizeof(T)) == 0)
+        hipLaunchKernelGGL((batched_kernel<Node, Seg, RowsInFlight<Node>::value, false>), dim3(sh.blocks),
+                           dim3(sh.wpb * WAVE), 0, st, nd, seg, x, nseg, order, ws.item_off, sh.lwt,
+                           static_cast<T *>(ws.roots), ws.seg_cnt, ws.ctrs, res);
+    else
+        hipLaunchKernelGGL((batched_kernel<Node, Seg, RowsInFlight<Node>::value, true>), dim3(sh.blocks),
+                           dim3(sh.wpb * WAVE), 0, st, nd, seg, x, nseg, order, ws.item_off, sh.lwt,
+                           static_cast<T *>(ws.roots), ws.seg_cnt, ws.ctrs, res);
     return (int)hipGetLastError();
 }
 
@@ -441,7 +449,7 @@ static void launch_class(const Node &nd, const SegList &seg, int64_t n, const in
     const int64_t waves = items < maxw ? items : maxw;
     const int wpb = waves >= 4 * (int64_t)cus() ? 4 : 1;
     const int blocks = (int)((waves + wpb - 1) / wpb);
-    hipLaunchKernelGGL((batched_kernel<Node, SegList, RowsInFlight<Node>::value>), dim3(blocks), dim3(wpb * WAVE), 0,
+    hipLaunchKernelGGL((batched_kernel<Node, SegList, RowsInFlight<Node>::value, true>), dim3(blocks), dim3(wpb * WAVE), 0,
                        st, nd, seg, (const T *)nullptr, n, (const int32_t *)nullptr, item_off, lwt,
                        static_cast<T *>(roots), seg_cnt, ctr, res);
 }
@@ -540,10 +548,12 @@ static int plan_enqueue_any(PlanImpl &P, const BatchShape &sh, hipStream_t st)
 // computes the same tree, so the choice never changes a result.
 static int autotune(PlanImpl &P, hipStream_t st)
 {
+    // work item size x block size x waves per CU (the waves that fit at once depend on
+    // the kernel's registers; timing finds the best count)
     std::vector<BatchShape> cands;
     for (int lwt : {0, 1, 2, 3})
         for (int wpb : {4, 8})
-            for (int per_cu : {1, 2, 4}) cands.push_back(BatchShape{lwt, wpb, cus() * per_cu * 8 / wpb});
+            for (int wpc : {8, 12, 16, 24}) cands.push_back(BatchShape{lwt, wpb, cus() * wpc / wpb});
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return (int)hipErrorUnknown;
     float best = 1e30f;

@@ -104,45 +104,4 @@ struct RowsInFlight<MaxNode<double>> {
     static constexpr int value = 8;
 };
 
-struct BatchShape {
-    int lwt;     // log2(tiles per item)
-    int wpb;     // waves per block
-    int blocks;  // resident blocks
-};
-
-struct BatchWorkspace {
-    void *roots = nullptr;
-    size_t roots_cap = 0;  // bytes
-    int64_t *item_off = nullptr;
-    size_t item_cap = 0;  // entries
-    unsigned int *seg_cnt = nullptr;
-    size_t seg_cap = 0;  // entries
-    unsigned long long *ctrs = nullptr;
-};
-
-int release_workspaces();
-int release_batch_workspaces();
-// One class of a request batch: requests [a, a + n) of the batch (sorted by class) share
-// dtype and p; items work items at lwt (from request_class_items).
-struct RequestClass {
-    int dtype;
-    double p;
-    int64_t a, n;
-    int64_t items;
-    int lwt;
-};
-// Item offsets (n + 1 entries) of n requests of one dtype with lengths lens; returns the
-// log2(tiles per item) they are computed for.
-int request_class_items(int dtype, const int64_t *lens, int64_t n, int64_t *item_off);
-// Enqueues one request batch on st: a stage kernel copies the descriptor words from
-// h_src (device view of host-mapped memory; ptrs[nreq] | lens[nreq] | incs[nreq] | item
-// offsets, class c's n_c + 1 entries at 3 nreq + a_c + c) to d_desc (device, at least
-// 4 nreq + ncls words) and clears the class counters; then one batched launch per class
-// writes request i of class c to res_d[a_c + i] or res_s[a_c + i].  ptrs are addresses of
-// logical element 0 (moved for negative strides); lengths are >= 0.
-int enqueue_request_batch(const void *h_src, void *d_desc, int64_t nreq, const RequestClass *cls, int ncls,
-                          double *res_d, float *res_s, BatchWorkspace &ws, hipStream_t st);
-void release_batch_ws(BatchWorkspace &w);
-int set_launch_shape(int wpb, int wt);
-
 }  // namespace vnp

@@ -14,6 +14,7 @@
 #include <utility>
 
 #include "../../include/vnp.h"
+#include "vnp_batch.hpp"
 #include "vnp_internal.hpp"
 #include "vnp_nodes_p.hpp"
 
@@ -200,7 +201,7 @@ static int run_norm(const Node &nd, int64_t n, const typename Node::T *x, int64_
     int rc = get_workspace(stream, sizeof(T) * (size_t)nblocks, &ws);
     if (rc) return rc;
     const T *base = incx >= 0 ? x : x + (n - 1) * (-incx);
-    const bool fast = incx == 1 && ((uintptr_t)x & 15) == 0;
+    const bool fast = incx == 1 && ((uintptr_t)x % sizeof(T)) == 0;
     launch(nd, fast, dim3((unsigned)nblocks), dim3((unsigned)(s.wpb * WAVE)), st, base, n, incx, ntiles, s.lwt,
            static_cast<T *>(ws->roots), ws->ticket, res);
     return (int)hipGetLastError();

@@ -25,6 +25,7 @@
 #include <vector>
 
 #include "../../include/vnp_server.h"
+#include "vnp_batch.hpp"
 #include "vnp_internal.hpp"
 
 namespace {

@@ -36,12 +36,17 @@ constexpr int ROWS = 64;  // rows per tile: depth of the per-lane row tree is 6
 
 typedef double d2v __attribute__((ext_vector_type(2)));
 typedef float f4v __attribute__((ext_vector_type(4)));
+// The same vectors at the alignment of one element: a contiguous input needs only its
+// natural alignment for the 16-byte loads (the target allows dword-aligned vector loads).
+typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
 
 template <typename T>
 struct Vec;
 template <>
 struct Vec<double> {
     using V = d2v;
+    using VU = d2u;
     static constexpr int N = 2;
     __device__ static double get(const V &v, int c) { return v[c]; }
     __device__ static V zero() { return V{0.0, 0.0}; }
@@ -49,6 +54,7 @@ struct Vec<double> {
 template <>
 struct Vec<float> {
     using V = f4v;
+    using VU = f4u;
     static constexpr int N = 4;
     __device__ static float get(const V &v, int c) { return v[c]; }
     __device__ static V zero() { return V{0.f, 0.f, 0.f, 0.f}; }
@@ -64,9 +70,10 @@ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 // tile_base + r * (64 VEC) + lane * VEC + c.
 // ---------------------------------------------------------------------------------
 template <typename T>
-struct LoadFast {  // contiguous, 16-byte aligned, full tile
+struct LoadFast {  // contiguous, naturally aligned, full tile
     using V = typename Vec<T>::V;
-    const V *__restrict__ p;  // tile base
+    using VU = typename Vec<T>::VU;
+    const VU *__restrict__ p;  // tile base
     __device__ V operator()(int r, int lane) const { return __builtin_nontemporal_load(p + r * WAVE + lane); }
 };
 
@@ -195,7 +202,7 @@ constexpr int MAX_LWT = 12;  // a wave covers at most 2^12 tiles
 // ntiles are padding and are skipped exactly): per-lane row trees (rows in groups of U),
 // then columns, then lanes, for each tile; then the tiles, by a binary-counter stack of
 // tile roots.  One group of rows is always in flight while the previous one is reduced,
-// across tile boundaries.  FAST: contiguous 16-byte-aligned input.
+// across tile boundaries.  FAST: contiguous, naturally aligned input.
 template <class Node, int U, bool FAST>
 __device__ __forceinline__ typename Node::T wave_root(const Node &nd, const typename Node::T *x, int64_t n,
                                                       int64_t inc, int64_t t0, int64_t ntiles, int lwt, int lane)
@@ -217,7 +224,8 @@ __device__ __forceinline__ typename Node::T wave_root(const Node &nd, const type
     T rstk[C][LG + 1];
     T tstk[MAX_LWT + 1];
 
-    // binary counter over tile roots; entries stay wave-uniform
+    // binary counter over tile roots; entries stay wave-uniform.  After the last of
+    // 2^MAX_LWT pushes the carry reaches the top level.
     auto push_tile = [&](T t, int idx) {
         bool carry = true;
 #pragma unroll
@@ -227,6 +235,7 @@ __device__ __forceinline__ typename Node::T wave_root(const Node &nd, const type
             if (carry && !bit) tstk[l] = t;
             carry = carry && bit;
         }
+        if (carry) tstk[MAX_LWT] = t;
     };
 
     auto step = [&](const V(&v)[U], int q) {
@@ -283,12 +292,11 @@ __device__ __forceinline__ typename Node::T wave_root(const Node &nd, const type
         __builtin_amdgcn_sched_barrier(0);
         step(b, q + 1);
     };
-    using TV = typename VV::V;
     auto generic = [&](int64_t t) { return LoadGeneric<T>{x, inc, n, t * TE}; };
     if constexpr (FAST) {
         const int64_t full = n / TE;  // tiles entirely inside [0, n)
         const int kfull = full <= t0 ? 0 : (full - t0 < ktiles ? (int)(full - t0) : ktiles);
-        auto fast = [&](int64_t t) { return LoadFast<T>{reinterpret_cast<const TV *>(x + t * TE)}; };
+        auto fast = [&](int64_t t) { return LoadFast<T>{reinterpret_cast<const typename VV::VU *>(x + t * TE)}; };
         if (kfull > 0) stream_groups(fast, 0, kfull * G);
         if (kfull < ktiles) push_tile(uniform(generic_tile_root<Node, U>(nd, x, n, inc, t0 + kfull, lane)), kfull);
     } else {
@@ -299,7 +307,7 @@ __device__ __forceinline__ typename Node::T wave_root(const Node &nd, const type
     T cur = T(0);
     bool any = false;
 #pragma unroll
-    for (int l = 0; l < MAX_LWT; ++l) {
+    for (int l = 0; l <= MAX_LWT; ++l) {
         if (l < lwt + 1 && ((ktiles >> l) & 1)) {
             cur = any ? uniform(nd.node(tstk[l], cur)) : tstk[l];
             any = true;

@@ -1,0 +1,97 @@
+"""Parity at the benchmark sizes, in the launch configuration the benchmark times.
+
+One vector of n = 2^30 (binary64 and binary32; the plain range and the overflow-prone,
+large finite and subnormal ranges) against the oracle (A: R with the correctly rounded
+hypot) and the exact norm; the device-generated input is checked to be the host input.
+p-norms at n = 2^28 against the binary128 reference, against the oracle where its node
+is cheap (p = 1), exact power-of-two scaling, and p = 2 against the Frobenius call.
+The oracle's A_p with a correctly rounded pow per node needs minutes at n = 2^28, so
+the other p are pinned to it at the smaller sizes of the regular parity tests."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import vnp_gen
+from gpu_util import assert_parity, bits
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+vnp = pytest.importorskip("paper_2509_06220_amd")
+
+C1_CASES = [("f64", "c1", False), ("f64", "c1_overflow_d", True), ("f64", "c1_bigfinite_d", False),
+            ("f64", "c1_subnormal_d", False), ("f32", "c1", False), ("f32", "c1_overflow_s", True),
+            ("f32", "c1_subnormal_s", False)]
+
+
+@pytest.fixture(autouse=True)
+def _default_shape():
+    vnp.set_launch_shape(0, 0)
+    yield
+    vnp.set_launch_shape(0, 0)
+    torch.cuda.empty_cache()
+
+
+def inputs(fmt, rec):
+    r = vnp_gen.recipe(rec)
+    n = r["n"]
+    dt = torch.float64 if fmt == "f64" else torch.float32
+    xd = torch.empty(n, dtype=dt, device="cuda")
+    vnp_gen.dev_fill(xd, kind=r["kind"], lo=r["lo"], hi=r["hi"], seed=r["seed"], stream=r["stream"])
+    xh = vnp_gen.host_fill(n, dtype=fmt, kind=r["kind"], lo=r["lo"], hi=r["hi"], seed=r["seed"], stream=r["stream"])
+    idx = np.unique(np.concatenate([np.linspace(0, n - 1, 8193).astype(np.int64), np.arange(n - 64, n)]))
+    got = xd[torch.from_numpy(idx).cuda()].cpu().numpy()
+    ui = np.uint64 if fmt == "f64" else np.uint32
+    assert np.array_equal(got.view(ui), xh[idx].view(ui)), "device generator differs from the host generator"
+    return xd, xh
+
+
+def eps(fmt):
+    return 2.0 ** -53 if fmt == "f64" else 2.0 ** -24
+
+
+@pytest.mark.parametrize("fmt,rec,overflows", C1_CASES)
+def test_c1_full_size(fmt, rec, overflows):
+    print(f"full size {fmt} {rec}", flush=True)
+    xd, xh = inputs(fmt, rec)
+    n = xh.size
+    g = vnp.nrmf(xd).item()
+    o = oracle.nrmf(xh, "A")
+    if overflows:
+        assert g == math.inf and o == math.inf, (g, o)
+        return
+    assert_parity(g, o, n, fmt, rec)
+    ex = oracle.exact_nrm2(xh)
+    print(f"  {rec} {fmt}: GPU {g!r}, oracle {o!r}, exact {ex!r}; error vs exact: GPU "
+          f"{abs(g - ex) / ex / eps(fmt):.3f} eps, oracle {abs(o - ex) / ex / eps(fmt):.3f} eps", flush=True)
+    if rec == "c1":
+        # the same bits from other launch shapes (waves per block, tiles per wave)
+        for wpb, wt in ((1, 1), (4, 8), (16, 4096)):
+            vnp.set_launch_shape(wpb, wt)
+            assert bits(vnp.nrmf(xd).item(), fmt) == bits(g, fmt), (wpb, wt)
+        vnp.set_launch_shape(0, 0)
+
+
+@pytest.mark.parametrize("p", [1.0, 1.5, 3.0, 4.5, 8.0])
+def test_c2_full_size(p):
+    print(f"full size p-norm p={p}", flush=True)
+    xd, xh = inputs("f64", "c2")
+    n = xh.size
+    g = vnp.nrmp(xd, p).item()
+    hi, lo = oracle.ref_pnorm(xh, p)
+    ref = hi + lo
+    tol = 2 * (math.ceil(math.log2(n)) + 1) * eps("f64")
+    assert abs(g - ref) <= tol * ref, (g, ref, (g - ref) / ref / eps("f64"))
+    print(f"  p={p}: GPU error vs binary128 reference {abs(g - ref) / ref / eps('f64'):.3f} eps", flush=True)
+    if p == 1.0:
+        assert_parity(g, oracle.nrmp(xh, 1.0, "A"), n, "f64", "p=1")
+    # exact power-of-two scaling (no node crosses the subnormal or overflow range)
+    xd.mul_(32.0)
+    assert bits(vnp.nrmp(xd, p).item(), "f64") == bits(32.0 * g, "f64")
+
+
+def test_c2_p2_is_frobenius():
+    xd, _ = inputs("f64", "c2")
+    assert bits(vnp.nrmp(xd, 2.0).item(), "f64") == bits(vnp.nrmf(xd).item(), "f64")

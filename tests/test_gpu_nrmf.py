@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import vnp_gen
-from gpu_util import assert_parity, fmt_of, to_dev
+from gpu_util import assert_parity, bits, fmt_of, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -66,6 +66,21 @@ def test_launch_shapes_are_bitwise_identical(fmt):
         vnp.set_launch_shape(0, 0)
         for _ in range(20):
             assert gpu_norm(x) == ref
+
+
+@pytest.mark.parametrize("fmt", ["f64", "f32"])
+def test_longest_runs_per_wave(fmt):
+    """Waves covering the maximum run of 2^12 tiles (all of it, and a ragged part) give
+    the default shape's bits."""
+    n = 4096 * (TS if fmt == "f32" else TD) + 12345
+    xh = vnp_gen.host_fill(n, dtype=fmt, kind="exp", lo=-20, hi=20, seed=17)
+    x = to_dev(xh)
+    ref = gpu_norm(x)
+    assert_parity(ref, oracle.nrmf(xh, "A"), n, fmt)
+    for wpb, wt in ((1, 4096), (2, 4096), (16, 4096), (4, 2048)):
+        print(f"{fmt} n={n} shape ({wpb}, {wt})", flush=True)
+        vnp.set_launch_shape(wpb, wt)
+        assert bits(gpu_norm(x), fmt) == bits(ref, fmt), (wpb, wt)
 
 
 @pytest.mark.parametrize("fmt", ["f64", "f32"])

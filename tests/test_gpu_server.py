@@ -69,6 +69,27 @@ def test_results_equal_alone_and_in_the_mix():
     srv.close()
 
 
+def test_long_requests_alone():
+    """Single long requests (one tile per work item, more than 512 run roots per request,
+    reduced in several passes) give the plain call's bits."""
+    srv = vnp.Server(pool_bytes=1 << 30, max_batch=8, streams=1, max_wait_us=0)
+    hs = torch.cuda.current_stream().cuda_stream
+    for dtype, n, incx in ((vnp.F64, (1 << 23) + 5, 1), (vnp.F32, (1 << 24) + 3, 1), (vnp.F64, (1 << 22) + 1, 2),
+                           (vnp.F64, (1 << 23) + 5, -1)):
+        esz = 8 if dtype == vnp.F64 else 4
+        span = (n - 1) * abs(incx) + 1
+        ptr = srv.alloc(span * esz)
+        vnp_gen.dev_fill_ptr(ptr, span, "f64" if dtype == vnp.F64 else "f32", kind="u11exp", lo=-30, hi=30,
+                             seed=9, stream=n, hip_stream=hs)
+        torch.cuda.synchronize()
+        for p in (2.0, 3.0):
+            print(f"long request dtype={dtype} n={n} incx={incx} p={p}", flush=True)
+            r = srv.wait(srv.submit(ptr, n, dtype, p, incx))
+            assert r.status == 0 and same(r.value, plain(ptr, n, dtype, p, incx))
+        srv.free(ptr)
+    srv.close()
+
+
 def test_concurrent_clients():
     srv = vnp.Server(pool_bytes=1 << 30, max_batch=128, streams=4, max_wait_us=0)
     reqs = make_requests(srv, 160, seed=2)
