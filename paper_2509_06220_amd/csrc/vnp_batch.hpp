@@ -18,9 +18,6 @@ struct BatchWorkspace {
     size_t roots_cap = 0;  // bytes
     int64_t *item_off = nullptr;
     size_t item_cap = 0;  // entries
-    unsigned int *seg_cnt = nullptr;
-    size_t seg_cap = 0;  // entries
-    unsigned long long *ctrs = nullptr;
 };
 
 int release_workspaces();
@@ -33,6 +30,7 @@ struct RequestClass {
     int64_t a, n;
     int64_t items;
     int lwt;
+    int multi;  // some request of the class spans more than one run
 };
 // Item offsets (n + 1 entries) of n requests of one dtype with lengths lens; returns the
 // log2(tiles per item) they are computed for.
@@ -41,7 +39,8 @@ int request_class_items(int dtype, const int64_t *lens, int64_t n, int64_t *item
 // h_src (device view of host-mapped memory; ptrs[nreq] | lens[nreq] | incs[nreq] | item
 // offsets, class c's n_c + 1 entries at 3 nreq + a_c + c) to d_desc (device, at least
 // 4 nreq + ncls words) and clears the class counters; then one batched launch per class
-// writes request i of class c to res_d[a_c + i] or res_s[a_c + i].  ptrs are addresses of
+// writes request i of class c to res_d[a_c + i] or res_s[a_c + i], followed by a finish
+// launch for classes with requests of several runs.  ptrs are addresses of
 // logical element 0 (moved for negative strides); lengths are >= 0.
 int enqueue_request_batch(const void *h_src, void *d_desc, int64_t nreq, const RequestClass *cls, int ncls,
                           double *res_d, float *res_s, BatchWorkspace &ws, hipStream_t st);

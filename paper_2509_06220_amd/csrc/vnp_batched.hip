@@ -1,19 +1,21 @@
 // Batched norms: many segments in one persistent launch (Novakovic, arXiv 2509.06220,
 // Sect. 3.1: norms of the columns of a multi-dimensional array).
 //
-// Work items are (segment, run of 2^lwt tiles of that segment).  Wave w of the grid
-// starts with item w and then pulls further items from an atomic counter, so long and
-// short segments share the GPU without a tail and a launch with little work costs no
-// atomics.  Each run's root is an aligned subtree of the segment's canonical tree (the
-// same tree the single-vector call uses), a segment of one run writes its result
-// directly, and the last run of a longer segment to finish (per-segment ticket) reduces
-// the run roots by the fixed tree.  A setup kernel, launched before the main kernel on
-// the same stream, turns the segment lengths into item offsets (prefix sums over the
-// processing order), writes +0 for empty segments and clears the item counter; the
-// per-segment tickets reset themselves.  A captured graph (setup + main kernel) can
-// therefore be replayed without clearing memory.
+// Work items are (segment, run of 2^lwt tiles of that segment), in a processing order
+// (longest segments first when the host knows the lengths).  Wave w of the grid takes
+// items w, w + W, w + 2W, ... (W waves, all resident), so the launch needs no atomics.
+// Each run's root is an aligned subtree of the segment's canonical tree (the same tree
+// the single-vector call uses).  A segment of one run writes its result directly; the
+// run roots of longer segments are written to the workspace, and a finish kernel
+// launched after the streaming kernel reduces them by the fixed tree.  Waves of the
+// streaming kernel never exchange data, so the kernel needs no release or acquire
+// (on a multi-XCD device those write back and invalidate the L2).  A setup kernel,
+// launched first on the same stream, turns the segment lengths into item offsets
+// (prefix sums over the processing order) and writes +0 for empty segments.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -95,14 +97,11 @@ __device__ __forceinline__ int64_t runs_of(int64_t len, int lwt)
 template <typename T, class Seg>
 __global__ void __launch_bounds__(1024)
     batched_setup_kernel(Seg seg, int64_t nseg, const int32_t *order, int lwt, int64_t n_total, int64_t items_cap,
-                         int64_t *item_off, T *res, unsigned long long *ctr)
+                         int64_t *item_off, T *res)
 {
     __shared__ int64_t part[1024];
     __shared__ int bad;
-    if (threadIdx.x == 0) {
-        bad = 0;
-        *ctr = 0;  // item counter of the main kernel that follows on this stream
-    }
+    if (threadIdx.x == 0) bad = 0;
     __syncthreads();
     const int64_t chunk = (nseg + blockDim.x - 1) / blockDim.x;
     const int64_t k0 = (int64_t)threadIdx.x * chunk;
@@ -177,24 +176,24 @@ __device__ typename Node::T wave_finish(const Node &nd, typename Node::T *r, int
             r[ck] = t;
         }
         cnt = nck;
-        // the wave's stores are visible to its own loads of the next pass
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // the next pass reads this wave's own stores
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
     return uniform(r[0]);
 }
 
 // ---------------------------------------------------------------------------------
-// Persistent batched kernel.  *ctr counts the items handed out beyond the first one of
-// each wave; it is zero at launch (cleared by the setup or stage kernel before it).
+// Streaming kernel: items -> run roots (a segment of one run: its result).
 // ---------------------------------------------------------------------------------
+constexpr int COARSE_MAX = 4096;  // LDS entries of the item-offset index (32 KiB)
+
 // GEN: segments may be strided or not element-aligned (the generic loader is compiled
 // in); without it every segment takes the vector-load path, which needs fewer registers.
 template <class Node, class Seg, int U, bool GEN>
 __global__ void __launch_bounds__(512)
     batched_kernel(Node nd, Seg seg, const typename Node::T *x, int64_t nseg, const int32_t *order,
-                   const int64_t *item_off, int lwt, typename Node::T *roots, unsigned int *seg_cnt,
-                   unsigned long long *ctr, typename Node::T *res)
+                   const int64_t *item_off, int lwt, typename Node::T *roots, typename Node::T *res)
 {
     using T = typename Node::T;
     constexpr int64_t TE = tile_elems<T>();
@@ -202,14 +201,27 @@ __global__ void __launch_bounds__(512)
     const int64_t total = item_off[nseg];
     const int wpb = (int)(blockDim.x / WAVE);
     const int64_t nwaves = (int64_t)gridDim.x * wpb;
-    // No lane-dependent branches in this loop: every wave-level step (fetch, ticket,
-    // stores of wave-uniform values) is executed by all lanes, with lane 0 contributing
-    // the increment, so the cross-lane reads always see one converged wave.
-    const unsigned long long one = lane == 0 ? 1ull : 0ull;
-    int64_t item = (int64_t)blockIdx.x * wpb + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
-    while (item < total) {
-        // processing position k: the last k with item_off[k] <= item
-        int64_t lo = 0, hi = nseg - 1;
+    // Coarse index of the item offsets in LDS: every stride-th entry (at most
+    // COARSE_MAX), so finding an item's segment takes LDS reads plus log2(stride)
+    // global reads.
+    extern __shared__ int64_t s_coarse[];
+    const int64_t stride = (nseg + COARSE_MAX - 1) / COARSE_MAX;  // >= 1
+    const int ncoarse = (int)((nseg + stride - 1) / stride);      // entries k = j * stride < nseg
+    for (int j = threadIdx.x; j < ncoarse; j += blockDim.x) s_coarse[j] = item_off[(int64_t)j * stride];
+    __syncthreads();
+    for (int64_t item = (int64_t)blockIdx.x * wpb + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+         item < total; item += nwaves) {
+        // processing position k: the last k with item_off[k] <= item (item < total)
+        int jlo = 0, jhi = ncoarse - 1;
+        while (jlo < jhi) {
+            const int mid = (jlo + jhi + 1) >> 1;
+            if (s_coarse[mid] <= item)
+                jlo = mid;
+            else
+                jhi = mid - 1;
+        }
+        int64_t lo = (int64_t)jlo * stride;
+        int64_t hi = lo + stride - 1 < nseg - 1 ? lo + stride - 1 : nseg - 1;
         while (lo < hi) {
             const int64_t mid = (lo + hi + 1) >> 1;
             if (item_off[mid] <= item)
@@ -233,32 +245,42 @@ __global__ void __launch_bounds__(512)
         } else {
             root = wave_root<Node, U, true>(nd, xs, len, 1, r << lwt, ntiles, lwt, lane);
         }
-        if (nruns == 1) {
-            res[s] = nd.finish(root);  // every lane stores the same value
-        } else {
+        // every lane stores the same value
+        if (nruns == 1)
+            res[s] = nd.finish(root);
+        else
             roots[item] = root;
-            const unsigned int old = (unsigned int)__builtin_amdgcn_readfirstlane((int)__hip_atomic_fetch_add(
-                &seg_cnt[s], lane == 0 ? 1u : 0u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT));
-            if (old == (unsigned int)(nruns - 1)) {
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                const T segroot = wave_finish(nd, roots + item_off[k], nruns, lane);
-                res[s] = nd.finish(segroot);
-                __hip_atomic_store(&seg_cnt[s], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
+    }
+}
+
+// Finish kernel: one wave per segment of several runs reduces its run roots (written by
+// the streaming kernel before it on the same stream) by the fixed tree.
+template <class Node>
+__global__ void __launch_bounds__(256)
+    batched_finish_kernel(Node nd, int64_t nseg, const int32_t *order, const int64_t *item_off,
+                          typename Node::T *roots, typename Node::T *res)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wpb = (int)(blockDim.x / WAVE);
+    const int64_t nwaves = (int64_t)gridDim.x * wpb;
+    const int64_t total = uniform64(item_off[nseg]);  // 0 when the setup rejected the offsets
+    for (int64_t k = (int64_t)blockIdx.x * wpb + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE)); k < nseg;
+         k += nwaves) {
+        const int64_t a = uniform64(item_off[k]), b = uniform64(item_off[k + 1]);
+        if (b - a > 1 && b <= total) {
+            const int64_t s = order ? order[k] : k;
+            res[s] = nd.finish(wave_finish(nd, roots + a, b - a, lane));
         }
-        item = nwaves + uniform64((int64_t)atomicAdd(ctr, one));
     }
 }
 
 // Stage kernel of a request batch: copies the batch's descriptor words from host-mapped
-// memory to device memory and clears the item counters of its class launches.
+// memory to device memory.
 __global__ void __launch_bounds__(1024)
-    stage_kernel(const unsigned long long *src, unsigned long long *dst, int64_t nwords, unsigned long long *ctrs,
-                 int nctrs)
+    stage_kernel(const unsigned long long *src, unsigned long long *dst, int64_t nwords)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += stride) dst[i] = src[i];
-    if (blockIdx.x == 0 && (int)threadIdx.x < nctrs) ctrs[threadIdx.x] = 0;
 }
 
 // ---------------------------------------------------------------------------------
@@ -267,14 +289,8 @@ __global__ void __launch_bounds__(1024)
 static int ensure_batch_ws(BatchWorkspace &w, size_t roots_bytes, size_t nseg, hipStream_t st)
 {
     hipError_t e;
-    if (!w.ctrs) {
-        e = hipMalloc(reinterpret_cast<void **>(&w.ctrs), 256);
-        if (e != hipSuccess) return (int)e;
-        e = hipMemset(w.ctrs, 0, 256);
-        if (e != hipSuccess) return (int)e;
-    }
-    const bool grow_roots = w.roots_cap < roots_bytes, grow_items = w.item_cap < nseg + 1, grow_seg = w.seg_cap < nseg;
-    if ((grow_roots && w.roots) || (grow_items && w.item_off) || (grow_seg && w.seg_cnt)) {
+    const bool grow_roots = w.roots_cap < roots_bytes, grow_items = w.item_cap < nseg + 1;
+    if ((grow_roots && w.roots) || (grow_items && w.item_off)) {
         e = hipStreamSynchronize(st);  // old buffers may be in use by queued work
         if (e != hipSuccess) return (int)e;
     }
@@ -294,16 +310,6 @@ static int ensure_batch_ws(BatchWorkspace &w, size_t roots_bytes, size_t nseg, h
         if (e != hipSuccess) return (int)e;
         w.item_cap = c;
     }
-    if (grow_seg) {
-        if (w.seg_cnt) (void)hipFree(w.seg_cnt);
-        w.seg_cnt = nullptr;
-        const size_t c = std::max<size_t>(std::max<size_t>(nseg, 2 * w.seg_cap), 4096);
-        e = hipMalloc(reinterpret_cast<void **>(&w.seg_cnt), c * sizeof(unsigned int));
-        if (e != hipSuccess) return (int)e;
-        e = hipMemset(w.seg_cnt, 0, c * sizeof(unsigned int));
-        if (e != hipSuccess) return (int)e;
-        w.seg_cap = c;
-    }
     return 0;
 }
 
@@ -311,8 +317,6 @@ static void free_batch_ws(BatchWorkspace &w)
 {
     if (w.roots) (void)hipFree(w.roots);
     if (w.item_off) (void)hipFree(w.item_off);
-    if (w.seg_cnt) (void)hipFree(w.seg_cnt);
-    if (w.ctrs) (void)hipFree(w.ctrs);
     w = BatchWorkspace{};
 }
 
@@ -350,25 +354,89 @@ static int cus()
 
 static BatchShape default_batch_shape() { return BatchShape{2, 8, cus() * 2}; }
 
-// Enqueue setup + main kernels for one batched workload (no allocation: ws must be large
-// enough: roots for nseg + total_elems / tile + 1 items).
+static size_t coarse_bytes(int64_t nseg)
+{
+    const int64_t stride = (nseg + COARSE_MAX - 1) / COARSE_MAX;
+    return sizeof(int64_t) * (size_t)((nseg + stride - 1) / stride);
+}
+
+// Blocks of wpb waves of kernel k that are resident on one compute unit at once (with
+// the largest coarse index).  Items are assigned statically, so a grid must not exceed
+// what is resident.  Cached per kernel instantiation and block size.
+template <typename K>
+static int resident_blocks(K k, int wpb)
+{
+    static int cache[17] = {};
+    if (wpb < 1 || wpb > 16) return 1;
+    if (!cache[wpb]) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, wpb * WAVE, sizeof(int64_t) * COARSE_MAX) !=
+                hipSuccess ||
+            nb < 1)
+            nb = 1;
+        cache[wpb] = nb;
+    }
+    return cache[wpb];
+}
+
+template <class Node, class Seg, bool GEN>
+static int launch_streaming(const Node &nd, const Seg &seg, const typename Node::T *x, int64_t nseg,
+                            const int32_t *order, const int64_t *item_off, int lwt, int wpb, int blocks, void *roots,
+                            typename Node::T *res, hipStream_t st)
+{
+    using T = typename Node::T;
+    auto k = batched_kernel<Node, Seg, RowsInFlight<Node>::value, GEN>;
+    const int fit = cus() * resident_blocks(k, wpb);
+    if (blocks > fit) blocks = fit;
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(wpb * WAVE), coarse_bytes(nseg), st, nd, seg, x, nseg, order, item_off,
+                       lwt, static_cast<T *>(roots), res);
+    return blocks;
+}
+
+template <class Node>
+static void launch_finish(const Node &nd, int64_t nseg, const int32_t *order, const int64_t *item_off, void *roots,
+                          typename Node::T *res, hipStream_t st)
+{
+    using T = typename Node::T;
+    const int64_t waves = std::min<int64_t>(nseg, (int64_t)cus() * 16);
+    const int wpb = waves >= 4 ? 4 : 1;
+    const int blocks = (int)((waves + wpb - 1) / wpb);
+    hipLaunchKernelGGL((batched_finish_kernel<Node>), dim3(blocks), dim3(wpb * WAVE), 0, st, nd, nseg, order, item_off,
+                       static_cast<T *>(roots), res);
+}
+
+// Whether a segment of the workload can span more than one run of 2^lwt tiles (then the
+// finish kernel is needed).
+template <typename T>
+static bool may_multi(const SegOffsets &, int) { return true; }
+template <typename T>
+static bool may_multi(const SegCols &c, int lwt)
+{
+    constexpr int64_t TE = tile_elems<T>();
+    return (c.m + TE - 1) / TE > ((int64_t)1 << lwt);
+}
+
+// Enqueue setup, streaming and (if needed) finish kernels for one batched workload (no
+// allocation: ws must hold roots for nseg + total_elems / tile + 1 items).  *used gets
+// the shape actually launched (blocks capped to what is resident).
 template <class Node, class Seg>
 static int enqueue_batched(const Node &nd, const Seg &seg, const typename Node::T *x, int64_t nseg,
                            int64_t n_total, const int32_t *order, const BatchShape &sh, BatchWorkspace &ws,
-                           typename Node::T *res, hipStream_t st)
+                           typename Node::T *res, hipStream_t st, BatchShape *used = nullptr)
 {
     using T = typename Node::T;
     const int64_t items_cap = (int64_t)(ws.roots_cap / sizeof(T));
     hipLaunchKernelGGL((batched_setup_kernel<T, Seg>), dim3(1), dim3(1024), 0, st, seg, nseg, order, sh.lwt,
-                       n_total, items_cap, ws.item_off, res, ws.ctrs);
+                       n_total, items_cap, ws.item_off, res);
+    int blocks;
     if (Seg::contiguous && ((uintptr_t)x % sizeof(T)) == 0)
-        hipLaunchKernelGGL((batched_kernel<Node, Seg, RowsInFlight<Node>::value, false>), dim3(sh.blocks),
-                           dim3(sh.wpb * WAVE), 0, st, nd, seg, x, nseg, order, ws.item_off, sh.lwt,
-                           static_cast<T *>(ws.roots), ws.seg_cnt, ws.ctrs, res);
+        blocks = launch_streaming<Node, Seg, false>(nd, seg, x, nseg, order, ws.item_off, sh.lwt, sh.wpb, sh.blocks,
+                                                    ws.roots, res, st);
     else
-        hipLaunchKernelGGL((batched_kernel<Node, Seg, RowsInFlight<Node>::value, true>), dim3(sh.blocks),
-                           dim3(sh.wpb * WAVE), 0, st, nd, seg, x, nseg, order, ws.item_off, sh.lwt,
-                           static_cast<T *>(ws.roots), ws.seg_cnt, ws.ctrs, res);
+        blocks = launch_streaming<Node, Seg, true>(nd, seg, x, nseg, order, ws.item_off, sh.lwt, sh.wpb, sh.blocks,
+                                                   ws.roots, res, st);
+    if (may_multi<T>(seg, sh.lwt)) launch_finish(nd, nseg, order, ws.item_off, ws.roots, res, st);
+    if (used) *used = BatchShape{sh.lwt, sh.wpb, blocks};
     return (int)hipGetLastError();
 }
 
@@ -440,48 +508,45 @@ int request_class_items(int dtype, const int64_t *lens, int64_t n, int64_t *item
 }
 
 template <class Node>
-static void launch_class(const Node &nd, const SegList &seg, int64_t n, const int64_t *item_off, int lwt,
-                         int64_t items, void *roots, unsigned int *seg_cnt, unsigned long long *ctr,
-                         typename Node::T *res, hipStream_t st)
+static void launch_class(const Node &nd, const SegList &seg, const RequestClass &k, const int64_t *item_off,
+                         void *roots, typename Node::T *res, hipStream_t st)
 {
-    using T = typename Node::T;
-    const int64_t maxw = (int64_t)cus() * 16;
-    const int64_t waves = items < maxw ? items : maxw;
+    // one wave per item up to what is resident; blocks of one wave spread small
+    // batches over all compute units
+    const int64_t waves = std::min<int64_t>(k.items, (int64_t)cus() * 16);
     const int wpb = waves >= 4 * (int64_t)cus() ? 4 : 1;
     const int blocks = (int)((waves + wpb - 1) / wpb);
-    hipLaunchKernelGGL((batched_kernel<Node, SegList, RowsInFlight<Node>::value, true>), dim3(blocks), dim3(wpb * WAVE), 0,
-                       st, nd, seg, (const T *)nullptr, n, (const int32_t *)nullptr, item_off, lwt,
-                       static_cast<T *>(roots), seg_cnt, ctr, res);
+    (void)launch_streaming<Node, SegList, true>(nd, seg, nullptr, k.n, nullptr, item_off, k.lwt, wpb, blocks, roots,
+                                                res, st);
+    if (k.multi) launch_finish(nd, k.n, nullptr, item_off, roots, res, st);
 }
 
 template <typename T>
-static void launch_class_p(const SegList &seg, int64_t n, const int64_t *item_off, int lwt, int64_t items,
-                           void *roots, unsigned int *seg_cnt, unsigned long long *ctr, T *res, double p, T cutoff,
-                           hipStream_t st)
+static void launch_class_p(const SegList &seg, const RequestClass &k, const int64_t *item_off, void *roots, T *res,
+                           T cutoff, hipStream_t st)
 {
-    const T pt = (T)p;
+    const T pt = (T)k.p;
     if (pt == T(2))
-        launch_class(HypNode<T>{}, seg, n, item_off, lwt, items, roots, seg_cnt, ctr, res, st);
+        launch_class(HypNode<T>{}, seg, k, item_off, roots, res, st);
     else if (pt == T(1))
-        launch_class(SumNode<T>{}, seg, n, item_off, lwt, items, roots, seg_cnt, ctr, res, st);
+        launch_class(SumNode<T>{}, seg, k, item_off, roots, res, st);
     else if (__builtin_isinf(pt) || pt >= cutoff)
-        launch_class(MaxNode<T>{}, seg, n, item_off, lwt, items, roots, seg_cnt, ctr, res, st);
+        launch_class(MaxNode<T>{}, seg, k, item_off, roots, res, st);
     else
-        launch_class(make_lp_node<T>(pt), seg, n, item_off, lwt, items, roots, seg_cnt, ctr, res, st);
+        launch_class(make_lp_node<T>(pt), seg, k, item_off, roots, res, st);
 }
 
 int enqueue_request_batch(const void *h_src, void *d_desc, int64_t nreq, const RequestClass *cls, int ncls,
                           double *res_d, float *res_s, BatchWorkspace &ws, hipStream_t st)
 {
     if (nreq <= 0 || ncls <= 0) return 0;
-    if (ncls > 32) return (int)hipErrorInvalidValue;
     int64_t roots = 0;
     for (int c = 0; c < ncls; ++c) roots += cls[c].items;
     int rc = ensure_batch_ws(ws, 8 * (size_t)(roots > 0 ? roots : 1), (size_t)nreq, st);
     if (rc) return rc;
     const int64_t nwords = 3 * nreq + nreq + ncls;
     hipLaunchKernelGGL(stage_kernel, dim3(1), dim3(1024), 0, st, static_cast<const unsigned long long *>(h_src),
-                       static_cast<unsigned long long *>(d_desc), nwords, ws.ctrs, ncls);
+                       static_cast<unsigned long long *>(d_desc), nwords);
     const int64_t *w = static_cast<const int64_t *>(d_desc);
     const void *const *ptrs = reinterpret_cast<const void *const *>(w);
     int64_t roots_off = 0;
@@ -492,11 +557,9 @@ int enqueue_request_batch(const void *h_src, void *d_desc, int64_t nreq, const R
         const int64_t *item_off = w + 3 * nreq + k.a + c;
         void *rt = static_cast<char *>(ws.roots) + 8 * roots_off;
         if (k.dtype == VNP_F32)
-            launch_class_p<float>(seg, k.n, item_off, k.lwt, k.items, rt, ws.seg_cnt + k.a, ws.ctrs + c,
-                                  res_s + k.a, k.p, 0x1p24f, st);
+            launch_class_p<float>(seg, k, item_off, rt, res_s + k.a, 0x1p24f, st);
         else
-            launch_class_p<double>(seg, k.n, item_off, k.lwt, k.items, rt, ws.seg_cnt + k.a, ws.ctrs + c,
-                                   res_d + k.a, k.p, 0x1p53, st);
+            launch_class_p<double>(seg, k, item_off, rt, res_d + k.a, 0x1p53, st);
         roots_off += k.items;
     }
     return (int)hipGetLastError();
@@ -522,26 +585,27 @@ struct PlanImpl {
 };
 
 template <class Node>
-static int plan_enqueue(const Node &nd, PlanImpl &P, const BatchShape &sh, hipStream_t st)
+static int plan_enqueue(const Node &nd, PlanImpl &P, const BatchShape &sh, hipStream_t st, BatchShape *used)
 {
     using T = typename Node::T;
     return enqueue_batched(nd, SegOffsets{P.offsets}, static_cast<const T *>(P.x), P.nseg, P.n_total, P.order, sh,
-                           P.ws, static_cast<T *>(P.res), st);
+                           P.ws, static_cast<T *>(P.res), st, used);
 }
 
 template <typename T>
-static int plan_enqueue_p(PlanImpl &P, const BatchShape &sh, hipStream_t st, T cutoff)
+static int plan_enqueue_p(PlanImpl &P, const BatchShape &sh, hipStream_t st, T cutoff, BatchShape *used)
 {
     const T p = (T)P.p;
-    if (p == T(2)) return plan_enqueue(HypNode<T>{}, P, sh, st);
-    if (p == T(1)) return plan_enqueue(SumNode<T>{}, P, sh, st);
-    if (__builtin_isinf(p) || p >= cutoff) return plan_enqueue(MaxNode<T>{}, P, sh, st);
-    return plan_enqueue(make_lp_node<T>(p), P, sh, st);
+    if (p == T(2)) return plan_enqueue(HypNode<T>{}, P, sh, st, used);
+    if (p == T(1)) return plan_enqueue(SumNode<T>{}, P, sh, st, used);
+    if (__builtin_isinf(p) || p >= cutoff) return plan_enqueue(MaxNode<T>{}, P, sh, st, used);
+    return plan_enqueue(make_lp_node<T>(p), P, sh, st, used);
 }
 
-static int plan_enqueue_any(PlanImpl &P, const BatchShape &sh, hipStream_t st)
+static int plan_enqueue_any(PlanImpl &P, const BatchShape &sh, hipStream_t st, BatchShape *used = nullptr)
 {
-    return P.dtype == VNP_F32 ? plan_enqueue_p<float>(P, sh, st, 0x1p24f) : plan_enqueue_p<double>(P, sh, st, 0x1p53);
+    return P.dtype == VNP_F32 ? plan_enqueue_p<float>(P, sh, st, 0x1p24f, used)
+                              : plan_enqueue_p<double>(P, sh, st, 0x1p53, used);
 }
 
 // Times candidate shapes (median of 3 launches each) and keeps the fastest.  Every shape
@@ -558,10 +622,18 @@ static int autotune(PlanImpl &P, hipStream_t st)
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return (int)hipErrorUnknown;
     float best = 1e30f;
     BatchShape best_s = P.shape;
+    const char *lg = getenv("VNP_AUTOTUNE_LOG");  // set to 1: print every candidate's time
+    const bool log = lg && lg[0] == '1';
     int rc = 0;
-    for (const BatchShape &c : cands) {
-        rc = plan_enqueue_any(P, c, st);  // warm-up
+    std::vector<BatchShape> seen;
+    for (const BatchShape &want : cands) {
+        BatchShape c;
+        rc = plan_enqueue_any(P, want, st, &c);  // warm-up; c: the shape launched (resident blocks)
         if (rc) break;
+        bool dup = false;
+        for (const BatchShape &o : seen) dup = dup || (o.lwt == c.lwt && o.wpb == c.wpb && o.blocks == c.blocks);
+        if (dup) continue;
+        seen.push_back(c);
         float t[3];
         for (int r = 0; r < 3 && !rc; ++r) {
             (void)hipEventRecord(a, st);
@@ -572,6 +644,9 @@ static int autotune(PlanImpl &P, hipStream_t st)
         }
         if (rc) break;
         std::sort(t, t + 3);
+        if (log)
+            fprintf(stderr, "vnp autotune: tiles/item %d, waves/block %d, blocks %d: %.4f ms\n", 1 << c.lwt, c.wpb,
+                    c.blocks, t[1]);
         if (t[1] < best) {
             best = t[1];
             best_s = c;

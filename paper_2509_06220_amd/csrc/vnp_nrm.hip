@@ -1,10 +1,13 @@
 // Single-vector norms: xNRMF and xNRMP of Novakovic, arXiv 2509.06220 (Sect. 1, 3, 4),
-// on the canonical tree of vnp_tree.hpp, in one kernel launch.
+// on the canonical tree of vnp_tree.hpp.
 //
 // Launch: each wave reduces WT consecutive tiles, each block WPB consecutive waves; the
-// block root goes to a per-stream workspace, and the last block to finish (atomic
-// ticket, agent-scope release/acquire) reduces the block roots by the same fixed tree
-// and writes the result.  All launch shapes give bitwise identical results.
+// block roots go to a per-stream workspace and a one-block finish kernel, launched after
+// the streaming kernel on the same stream, reduces them by the same fixed tree and
+// writes the result (a grid of one block writes it directly).  The streaming kernel's
+// blocks never exchange data, so it needs no release or acquire, which on a multi-XCD
+// device write back and invalidate the L2.  All launch shapes give bitwise identical
+// results.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
@@ -26,11 +29,10 @@ namespace vnp {
 template <class Node, int U, bool FAST>
 __global__ void __launch_bounds__(1024)
     nrm_kernel(Node nd, const typename Node::T *x, int64_t n, int64_t inc, int64_t ntiles, int lwt,
-               typename Node::T *roots, unsigned int *ticket, typename Node::T *res)
+               typename Node::T *roots, typename Node::T *res)
 {
     using T = typename Node::T;
-    __shared__ T sbuf[1024];
-    __shared__ unsigned int s_last;
+    __shared__ T sbuf[16];
     const int lane = threadIdx.x & (WAVE - 1);
     // wave index: uniform within the wave (tell the compiler, so the loops stay scalar)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -40,22 +42,23 @@ __global__ void __launch_bounds__(1024)
     const T r = wave_root<Node, U, FAST>(nd, x, n, inc, t0, ntiles, lwt, lane);
     if (lane == 0) sbuf[wave] = r;
     lds_tree(nd, sbuf, wpb);
-    if (gridDim.x == 1) {
-        if (threadIdx.x == 0) *res = nd.finish(sbuf[0]);
-        return;
-    }
     if (threadIdx.x == 0) {
-        roots[blockIdx.x] = sbuf[0];
-        s_last = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+        if (gridDim.x == 1)
+            *res = nd.finish(sbuf[0]);
+        else
+            roots[blockIdx.x] = sbuf[0];
     }
-    __syncthreads();
-    if (!s_last) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    const T root = block_finish(nd, roots, (int64_t)gridDim.x, sbuf);
-    if (threadIdx.x == 0) {
-        *res = nd.finish(root);
-        __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+}
+
+// Fixed tree over the block roots of the streaming kernel (one block).
+template <class Node>
+__global__ void __launch_bounds__(256)
+    nrm_finish_kernel(Node nd, typename Node::T *roots, int64_t count, typename Node::T *res)
+{
+    using T = typename Node::T;
+    __shared__ T sbuf[256];
+    const T root = block_finish(nd, roots, count, sbuf);
+    if (threadIdx.x == 0) *res = nd.finish(root);
 }
 
 template <typename T>
@@ -112,7 +115,6 @@ static Shape choose_shape(int64_t ntiles)
 struct Workspace {
     void *roots = nullptr;  // block roots
     size_t roots_bytes = 0;
-    unsigned int *ticket = nullptr;
 };
 
 static std::mutex g_ws_mu;
@@ -125,12 +127,6 @@ static int get_workspace(void *stream, size_t roots_bytes, Workspace **out)
     if (e != hipSuccess) return (int)e;
     std::lock_guard<std::mutex> lk(g_ws_mu);
     Workspace &w = g_ws[std::make_pair(dev, stream)];
-    if (!w.ticket) {
-        e = hipMalloc(reinterpret_cast<void **>(&w.ticket), 256);
-        if (e != hipSuccess) return (int)e;
-        e = hipMemset(w.ticket, 0, 256);
-        if (e != hipSuccess) return (int)e;
-    }
     if (w.roots_bytes < roots_bytes) {
         if (w.roots) {
             // the old buffer may still be in use by work queued on this stream
@@ -157,7 +153,6 @@ int release_workspaces()
     for (auto it = g_ws.begin(); it != g_ws.end();) {
         if (it->first.first == dev) {
             if (it->second.roots) (void)hipFree(it->second.roots);
-            if (it->second.ticket) (void)hipFree(it->second.ticket);
             it = g_ws.erase(it);
         } else {
             ++it;
@@ -171,15 +166,16 @@ int release_workspaces()
 // ---------------------------------------------------------------------------------
 template <class Node>
 static void launch(const Node &nd, bool fast, dim3 grid, dim3 block, hipStream_t st, const typename Node::T *x,
-                   int64_t n, int64_t inc, int64_t ntiles, int lwt, typename Node::T *roots, unsigned *ticket,
-                   typename Node::T *res)
+                   int64_t n, int64_t inc, int64_t ntiles, int lwt, typename Node::T *roots, typename Node::T *res)
 {
     if (fast)
-        hipLaunchKernelGGL((nrm_kernel<Node, RowsInFlight<Node>::value, true>), grid, block, 0, st, nd, x, n, inc, ntiles, lwt, roots,
-                           ticket, res);
+        hipLaunchKernelGGL((nrm_kernel<Node, RowsInFlight<Node>::value, true>), grid, block, 0, st, nd, x, n, inc,
+                           ntiles, lwt, roots, res);
     else
-        hipLaunchKernelGGL((nrm_kernel<Node, RowsInFlight<Node>::value, false>), grid, block, 0, st, nd, x, n, inc, ntiles, lwt, roots,
-                           ticket, res);
+        hipLaunchKernelGGL((nrm_kernel<Node, RowsInFlight<Node>::value, false>), grid, block, 0, st, nd, x, n, inc,
+                           ntiles, lwt, roots, res);
+    if (grid.x > 1)
+        hipLaunchKernelGGL((nrm_finish_kernel<Node>), dim3(1), dim3(256), 0, st, nd, roots, (int64_t)grid.x, res);
 }
 
 template <class Node>
@@ -203,7 +199,7 @@ static int run_norm(const Node &nd, int64_t n, const typename Node::T *x, int64_
     const T *base = incx >= 0 ? x : x + (n - 1) * (-incx);
     const bool fast = incx == 1 && ((uintptr_t)x % sizeof(T)) == 0;
     launch(nd, fast, dim3((unsigned)nblocks), dim3((unsigned)(s.wpb * WAVE)), st, base, n, incx, ntiles, s.lwt,
-           static_cast<T *>(ws->roots), ws->ticket, res);
+           static_cast<T *>(ws->roots), res);
     return (int)hipGetLastError();
 }
 

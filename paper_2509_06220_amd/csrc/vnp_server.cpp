@@ -182,16 +182,16 @@ int vnp_server::launch(Slot &s, std::vector<Pending> &reqs, int *nlaunch)
                 rd[i] = 0.0;
         }
         if (classes.empty() || !same_class(reqs[(size_t)classes.back().a].req, q))
-            classes.push_back(vnp::RequestClass{q.dtype, q.p, i, 1, 0, 0});
+            classes.push_back(vnp::RequestClass{q.dtype, q.p, i, 1, 0, 0, 0});
         else
             classes.back().n += 1;
     }
-    if (classes.size() > 32) return (int)hipErrorInvalidValue;
     for (size_t c = 0; c < classes.size(); ++c) {
         vnp::RequestClass &k = classes[c];
         int64_t *off = w + 3 * n + k.a + (int64_t)c;
         k.lwt = vnp::request_class_items(k.dtype, hl + k.a, k.n, off);
         k.items = off[k.n];
+        for (int64_t i = 0; i < k.n && !k.multi; ++i) k.multi = off[i + 1] - off[i] > 1;
         *nlaunch += k.items > 0 ? 1 : 0;
     }
     int rc = vnp::enqueue_request_batch(s.h_desc_dev, s.d_desc, n, classes.data(), (int)classes.size(),

@@ -157,7 +157,9 @@ __device__ __forceinline__ float uniform(float v)
 }
 
 // Root of one tile through the generic loader (used for the partial tail tile of a
-// contiguous input, kept out of line so the vector-load loop keeps its registers).
+// contiguous input, kept out of line so the vector-load loop keeps its registers).  Row
+// groups past the end of the vector hold only zeros; they are not loaded, and the
+// partly filled group stack is combined as the zero-padded tree (node(a, 0) = a).
 template <class Node, int U>
 __device__ __noinline__ typename Node::T generic_tile_root(Node nd, const typename Node::T *x, int64_t n, int64_t inc,
                                                            int64_t t, int lane)
@@ -168,10 +170,13 @@ __device__ __noinline__ typename Node::T generic_tile_root(Node nd, const typena
     constexpr int C = VV::N;
     constexpr int G = ROWS / U;
     constexpr int LG = ilog2(G);
-    const LoadGeneric<T> ld{x, inc, n, t * tile_elems<T>()};
+    const int64_t base = t * tile_elems<T>();
+    const LoadGeneric<T> ld{x, inc, n, base};
+    const int64_t rows = (n - base + WAVE * C - 1) / (WAVE * C);  // rows holding elements, >= 1
+    const int gn = rows >= G * U ? G : (int)((rows + U - 1) / U);  // wave-uniform
     T rstk[C][LG + 1];
 #pragma unroll 1
-    for (int g = 0; g < G; ++g) {
+    for (int g = 0; g < gn; ++g) {
         V v[U];
         load_rows<U>(v, ld, g, lane);
 #pragma unroll
@@ -187,11 +192,25 @@ __device__ __noinline__ typename Node::T generic_tile_root(Node nd, const typena
             push<Node, T, LG>(nd, rstk[c], w[0], g);
         }
     }
+    T col[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        T cur = T(0);
+        bool any = false;
+#pragma unroll
+        for (int l = 0; l <= LG; ++l) {
+            if ((gn >> l) & 1) {
+                cur = any ? nd.node(rstk[c][l], cur) : rstk[c][l];
+                any = true;
+            }
+        }
+        col[c] = cur;
+    }
     T r;
     if constexpr (C == 2) {
-        r = nd.node(rstk[0][LG], rstk[1][LG]);
+        r = nd.node(col[0], col[1]);
     } else {
-        r = nd.node(nd.node(rstk[0][LG], rstk[1][LG]), nd.node(rstk[2][LG], rstk[3][LG]));
+        r = nd.node(nd.node(col[0], col[1]), nd.node(col[2], col[3]));
     }
     return lane_tree(nd, r, lane);
 }
