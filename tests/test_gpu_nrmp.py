@@ -63,3 +63,41 @@ def test_pnorm_strides_and_specials(fmt):
     assert gpu_p(to_dev(y), math.inf) == math.inf
     ints = np.arange(-300, 301, dtype=x.dtype)
     assert gpu_p(to_dev(ints), 1.0) == float(np.abs(ints).sum())
+
+
+@pytest.mark.parametrize("fmt", ["f64", "f32"])
+@pytest.mark.parametrize("p", [0.5, 1.5, 3.0, 4.5, 8.0, 100.0])
+def test_pnode_accuracy(fmt, p):
+    """The device p node on 4096 pairs spanning magnitude ratios 1 .. 2^-80 (as two-element
+    segments, so each result is one leaf node) against the binary128 reference and the
+    oracle's Listing 5 node with a correctly rounded pow.  Bounds: binary64 4 max(1, 1/p)
+    eps (an absolute error in log2 Z reaches C multiplied by 1/p); binary32 (1.1 + ln2 / p)
+    eps: the final rounding of the binary64 evaluation plus the binary32 rounding of the
+    exponent 1/p, which the single-precision node uses (Sect. 4)."""
+    rng = np.random.default_rng(int(p * 1000) + (1 if fmt == "f32" else 0))
+    npairs = 4096
+    a = np.ldexp(rng.uniform(0.5, 1.0, npairs), rng.integers(-30, 30, npairs))
+    b = a * np.ldexp(rng.uniform(0.5, 1.0, npairs), -rng.integers(0, 80, npairs))
+    b[:64] = a[:64]  # equal operands
+    b[64:128] = np.nextafter(a[64:128], 0)
+    x = np.empty(2 * npairs)
+    x[0::2], x[1::2] = a, b
+    sign = rng.random(2 * npairs) < 0.5
+    x[sign] = -x[sign]
+    npdt = np.float64 if fmt == "f64" else np.float32
+    x = x.astype(npdt)
+    off = np.arange(0, 2 * npairs + 1, 2, dtype=np.int64)
+    g = vnp.nrm_batched(to_dev(x), to_dev(off), p=p).cpu().numpy().astype(np.float64)
+    eps = 2.0 ** -53 if fmt == "f64" else 2.0 ** -24
+    worst_ref = worst_or = 0.0
+    for i in range(npairs):
+        pair = x[2 * i:2 * i + 2]
+        hi, lo = oracle.ref_pnorm(pair, p)
+        ref = hi + lo
+        worst_ref = max(worst_ref, abs(g[i] - ref) / ref / eps)
+        o = float(oracle.nrmp(pair, p, "A"))
+        worst_or = max(worst_or, abs(g[i] - o) / o / eps)
+    print(f"p={p} {fmt}: node error vs binary128 {worst_ref:.3f} eps, vs oracle node {worst_or:.3f} eps", flush=True)
+    bound = 4.0 * max(1.0, 1.0 / p) if fmt == "f64" else 1.1 + math.log(2.0) / p
+    assert worst_ref <= bound, (worst_ref, bound)
+    assert worst_or <= 2 * bound + 1, (worst_or, bound)
