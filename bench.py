@@ -30,6 +30,33 @@ KERNEL_SOURCES = ["paper_2509_06220_amd/csrc/vnp_nrm.hip", "paper_2509_06220_amd
                   "paper_2509_06220_amd/csrc/vnp_node.hpp", "paper_2509_06220_amd/csrc/vnp_internal.hpp"]
 
 
+PNODE_SOURCES = ["paper_2509_06220_amd/csrc/vnp_nrm.hip", "paper_2509_06220_amd/csrc/vnp_tree.hpp",
+                 "paper_2509_06220_amd/csrc/vnp_nodes_p.hpp", "paper_2509_06220_amd/csrc/vnp_internal.hpp"]
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_fp64.json")
+FP64_PEAK_TFLOPS = 78.6
+
+
+def pnode_hash() -> str:
+    h = hashlib.sha256()
+    for p in PNODE_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def pnode_flops():
+    """FP64 FLOPs per DNRMP (p = 3, n = 2^28) launch from the committed counter summary, if
+    it matches the kernel sources."""
+    try:
+        with open(VALU_FILE) as f:
+            v = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if v.get("kernel_sha_p") != pnode_hash():
+        return None
+    return v.get("dnrmp_3", {}).get("flops_per_launch")
+
+
 def kernel_hash() -> str:
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
@@ -108,6 +135,13 @@ def extra_modes(torch, vnp, vnp_gen):
         for p in (1.0, 1.5, 3.0, 4.5, 8.0):
             _, per = time_steps(lambda: vnp.nrmp(xp, p, out=resp), 5, 1, s)
             out[f"dnrmp_p{p:g}_gbs"] = round(n * 8 / (statistics.mean(per) / 1e3) / 1e9, 1)
+            if p == 3.0:
+                fl = pnode_flops()  # the generic-p node is bound by the FP64 VALU
+                out["dnrmp_p3_roofline"] = {
+                    "bound": "alu", "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS,
+                    "achieved": None if fl is None else round(fl / (statistics.mean(per) / 1e3) / 1e12, 2),
+                    "frac": None if fl is None else round(fl / (statistics.mean(per) / 1e3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+                    "flops_per_launch": fl}
         del xp
     except Exception as e:  # noqa: BLE001 -- report, do not hide the headline
         out["error"] = repr(e)
@@ -241,6 +275,8 @@ def main():
     ap.add_argument("--serve-rates", default="5000,20000,80000")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy 5 times (scale of the HBM byte counters)")
+    ap.add_argument("--profile-op", default=None,
+                    help="only run one operation K times for a profiler: dnrmf, snrmf (n=2^30) or dnrmp:<p> (n=2^28)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (the multi-GPU sharding "
@@ -261,6 +297,37 @@ def main():
             vnp_gen.dev_copy(dst.data_ptr(), src.data_ptr(), nb, 0, torch.cuda.current_stream().cuda_stream)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": nb, "launches": 5}), flush=True)
+        return
+
+    if args.profile_op:
+        op = args.profile_op
+        if op in ("dnrmf", "snrmf"):
+            n, dt = 1 << 30, (torch.float64 if op == "dnrmf" else torch.float32)
+            xo = torch.empty(n, dtype=dt, device="cuda")
+            vnp_gen.dev_fill(xo, kind="exp", lo=-20, hi=20, seed=0)
+            fn = lambda: vnp.nrmf(xo)  # noqa: E731
+        elif op.startswith("dnrmp:"):
+            n, pv = 1 << 28, float(op.split(":", 1)[1])
+            xo = torch.empty(n, dtype=torch.float64, device="cuda")
+            vnp_gen.dev_fill(xo, kind="exp", lo=-10, hi=10, seed=0)
+            fn = lambda: vnp.nrmp(xo, pv)  # noqa: E731
+        else:
+            print(f"unknown --profile-op {op}", file=sys.stderr)
+            sys.exit(2)
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < 0.5:  # let clocks settle (untimed)
+            fn()
+            torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        dt_s = (time.perf_counter() - t0) / args.steps
+        print(json.dumps({"profile_op": op, "n": n, "launches": args.steps, "ms_per_call": round(dt_s * 1e3, 4),
+                          "gbs": round(n * xo.element_size() / dt_s / 1e9, 1)}), flush=True)
         return
 
     n = 1 << 30
