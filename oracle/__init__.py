@@ -210,6 +210,23 @@ def nrmp(x, p: float, algo: str = "A", lanes: int | None = None, threads: int | 
     raise ValueError(algo)
 
 
+def nrm_mat(a, m: int, ncols: int, lda: int, p: float = 2.0, threads: int | None = None):
+    """Frobenius (p = 2) or entrywise p-norm of the m x ncols column-major array stored in a
+    with leading dimension lda (Sect. 3.1): an array stored contiguously (lda == m) is one
+    vector; otherwise the norms of its columns are computed by the recursion (A) and then
+    reduced by the same recursion, in column order.  Rows m .. lda-1 are never read."""
+    a = _prep(a)
+    if m <= 0 or ncols <= 0:
+        return a.dtype.type(0.0)
+    if lda < m:
+        raise ValueError("lda < m")
+    one = (lambda v: nrmf(v, "A", threads=threads)) if p == 2.0 else (lambda v: nrmp(v, p, "A", threads=threads))
+    if lda == m:
+        return one(a[:m * ncols])
+    norms = np.array([one(a[j * lda:j * lda + m]) for j in range(ncols)], dtype=a.dtype)
+    return one(norms)
+
+
 def trace(n: int, lanes: int = 0):
     """Tree shape: list of (left, right) ids per node in completion order.
 
