@@ -143,6 +143,16 @@ def extra_modes(torch, vnp, vnp_gen):
                     "frac": None if fl is None else round(fl / (statistics.mean(per) / 1e3) / 1e12 / FP64_PEAK_TFLOPS, 4),
                     "flops_per_launch": fl}
         del xp
+        torch.cuda.empty_cache()
+        # norm of a 2^15 x 2^15 FP64 array stored with leading dimension 2^15 + 64 (column
+        # norms, then the tree over columns)
+        m = ncols = 1 << 15
+        lda = m + 64
+        A = torch.empty(lda * ncols, dtype=torch.float64, device="cuda")
+        vnp_gen.dev_fill(A, kind="exp", lo=-20, hi=20, seed=0)
+        _, per = time_steps(lambda: vnp.nrm_mat(A, m, ncols, lda, out=resp), 10, 2, s)
+        out["dnrmf_mat_2p15x2p15_gbs"] = round(m * ncols * 8 / (statistics.mean(per) / 1e3) / 1e9, 1)
+        del A
     except Exception as e:  # noqa: BLE001 -- report, do not hide the headline
         out["error"] = repr(e)
     return out

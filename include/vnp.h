@@ -101,6 +101,22 @@ int vnp_snrmp_batched(int64_t nseg, const int64_t *offsets, int64_t n_total, con
 int vnp_dnrmf_cols(int64_t m, int64_t ncols, const double *A, int64_t lda, double *res, void *stream);
 int vnp_snrmf_cols(int64_t m, int64_t ncols, const float *A, int64_t lda, float *res, void *stream);
 
+/* Norm of a whole array with a leading dimension (Sect. 3.1): the m x ncols column-major
+ * array A (column j at A + j lda; for a higher-dimensional A(LDA, N2, ..., Nk), ncols =
+ * N2 ... Nk).  Frobenius (xNRMF_MAT) or entrywise p-norm (xNRMP_MAT, p as in xNRMP).
+ * Stored contiguously (lda == m, or one column), the array is one vector: the result is
+ * bitwise that of vnp_xnrmf / vnp_xnrmp on its m ncols elements.  Otherwise the column
+ * norms (each bitwise the single-vector result of that column) are reduced by the perfect
+ * binary tree over the column index (zero-padded, with the same node), one value written
+ * to *res.  Rows m .. lda-1 are never read.  Device pointers; stream-ordered.
+ * Errors: m < 0 -> -1; ncols < 0 -> -2; A == NULL (with m, ncols > 0) -> -3;
+ * lda < max(1, m) or the array spans more than VNP_MAX_N elements -> -4; p <= 0 or NaN
+ * -> -5 (p variants); res == NULL -> -5 (-6 for the p variants). */
+int vnp_dnrmf_mat(int64_t m, int64_t ncols, const double *A, int64_t lda, double *res, void *stream);
+int vnp_snrmf_mat(int64_t m, int64_t ncols, const float *A, int64_t lda, float *res, void *stream);
+int vnp_dnrmp_mat(int64_t m, int64_t ncols, const double *A, int64_t lda, double p, double *res, void *stream);
+int vnp_snrmp_mat(int64_t m, int64_t ncols, const float *A, int64_t lda, float p, float *res, void *stream);
+
 /* ------------------------------------------------------------------------------------
  * Plans: one batched workload (fixed buffers and segment count) prepared once -- launch
  * shape chosen by timing candidates on `stream` when autotune is set (the shape never

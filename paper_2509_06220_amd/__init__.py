@@ -56,6 +56,10 @@ def lib():
             "vnp_plan_info": [vp, vp, vp, vp],
             "vnp_dnrmf_cols": [i64, i64, vp, i64, vp, vp],
             "vnp_snrmf_cols": [i64, i64, vp, i64, vp, vp],
+            "vnp_dnrmf_mat": [i64, i64, vp, i64, vp, vp],
+            "vnp_snrmf_mat": [i64, i64, vp, i64, vp, vp],
+            "vnp_dnrmp_mat": [i64, i64, vp, i64, d, vp, vp],
+            "vnp_snrmp_mat": [i64, i64, vp, i64, f, vp, vp],
             "vnp_set_launch_shape": [i, i],
             "vnp_finalize": [],
             "vnp_server_create": [vp, vp],
@@ -237,6 +241,25 @@ def nrmf_cols(A, m, ncols, lda, out=None, stream=None):
         out = torch.empty(ncols, dtype=A.dtype, device=A.device)
     fn = "vnp_dnrmf_cols" if A.dtype == torch.float64 else "vnp_snrmf_cols"
     _check(fn, getattr(lib(), fn)(m, ncols, A.data_ptr(), lda, out.data_ptr(), _stream(A, stream)))
+    return out
+
+
+def nrm_mat(A, m, ncols, lda, p=2.0, out=None, stream=None):
+    """Frobenius (p = 2) or entrywise p-norm of the column-major m x ncols array stored in A
+    with leading dimension lda (one value, a 0-d tensor)."""
+    import torch
+
+    if out is None:
+        out = torch.empty((), dtype=A.dtype, device=A.device)
+    d = A.dtype == torch.float64
+    s = _stream(A, stream)
+    if p == 2.0:
+        fn = "vnp_dnrmf_mat" if d else "vnp_snrmf_mat"
+        rc = getattr(lib(), fn)(m, ncols, A.data_ptr(), lda, out.data_ptr(), s)
+    else:
+        fn = "vnp_dnrmp_mat" if d else "vnp_snrmp_mat"
+        rc = getattr(lib(), fn)(m, ncols, A.data_ptr(), lda, float(p), out.data_ptr(), s)
+    _check(fn, rc)
     return out
 
 

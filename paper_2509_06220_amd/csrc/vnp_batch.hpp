@@ -18,6 +18,8 @@ struct BatchWorkspace {
     size_t roots_cap = 0;  // bytes
     int64_t *item_off = nullptr;
     size_t item_cap = 0;  // entries
+    void *vals = nullptr;  // intermediate segment norms (array norms)
+    size_t vals_cap = 0;   // bytes
 };
 
 int release_workspaces();

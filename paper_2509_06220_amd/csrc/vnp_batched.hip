@@ -274,6 +274,17 @@ __global__ void __launch_bounds__(256)
     }
 }
 
+// Fixed tree over vals[0..count) (the perfect binary tree over the zero-padded index, as
+// block_finish evaluates it) by one block; vals is overwritten.
+template <class Node>
+__global__ void __launch_bounds__(256)
+    values_finish_kernel(Node nd, typename Node::T *vals, int64_t count, typename Node::T *res)
+{
+    __shared__ typename Node::T sbuf[256];
+    const typename Node::T root = block_finish(nd, vals, count, sbuf);
+    if (threadIdx.x == 0) *res = nd.finish(root);
+}
+
 // Stage kernel of a request batch: copies the batch's descriptor words from host-mapped
 // memory to device memory.
 __global__ void __launch_bounds__(1024)
@@ -313,10 +324,29 @@ static int ensure_batch_ws(BatchWorkspace &w, size_t roots_bytes, size_t nseg, h
     return 0;
 }
 
+static int ensure_vals(BatchWorkspace &w, size_t bytes, hipStream_t st)
+{
+    if (w.vals_cap >= bytes) return 0;
+    hipError_t e;
+    if (w.vals) {
+        e = hipStreamSynchronize(st);  // the old buffer may be in use by queued work
+        if (e != hipSuccess) return (int)e;
+        (void)hipFree(w.vals);
+        w.vals = nullptr;
+        w.vals_cap = 0;
+    }
+    const size_t b = std::max<size_t>(bytes, 1 << 16);
+    e = hipMalloc(&w.vals, b);
+    if (e != hipSuccess) return (int)e;
+    w.vals_cap = b;
+    return 0;
+}
+
 static void free_batch_ws(BatchWorkspace &w)
 {
     if (w.roots) (void)hipFree(w.roots);
     if (w.item_off) (void)hipFree(w.item_off);
+    if (w.vals) (void)hipFree(w.vals);
     w = BatchWorkspace{};
 }
 
@@ -467,6 +497,41 @@ static int run_batched_p(const Seg &seg, const T *x, int64_t nseg, int64_t total
     if (p == T(1)) return run_batched(SumNode<T>{}, seg, x, nseg, total, res, stream);
     if (__builtin_isinf(p) || p >= cutoff) return run_batched(MaxNode<T>{}, seg, x, nseg, total, res, stream);
     return run_batched(make_lp_node<T>(p), seg, x, nseg, total, res, stream);
+}
+
+// Norm of an m x ncols array with leading dimension lda > m (Sect. 3.1): column norms
+// into the workspace, then the fixed tree over them.
+template <class Node>
+static int run_mat(const Node &nd, int64_t m, int64_t ncols, const typename Node::T *A, int64_t lda,
+                   typename Node::T *res, void *stream)
+{
+    using T = typename Node::T;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const BatchShape sh = default_batch_shape();
+    const int64_t total = (ncols - 1) * lda + m;
+    const int64_t items_cap = ncols + (total + tile_elems<T>() - 1) / tile_elems<T>() + 1;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    std::lock_guard<std::mutex> lk(g_bws_mu);
+    BatchWorkspace &ws = g_bws[std::make_pair(dev, stream)];
+    int rc = ensure_batch_ws(ws, sizeof(T) * (size_t)items_cap, (size_t)ncols, st);
+    if (!rc) rc = ensure_vals(ws, sizeof(T) * (size_t)ncols, st);
+    if (rc) return rc;
+    T *vals = static_cast<T *>(ws.vals);
+    rc = enqueue_batched(nd, SegCols{lda, m}, A, ncols, total, nullptr, sh, ws, vals, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL((values_finish_kernel<Node>), dim3(1), dim3(256), 0, st, nd, vals, ncols, res);
+    return (int)hipGetLastError();
+}
+
+template <typename T>
+static int run_mat_p(int64_t m, int64_t ncols, const T *A, int64_t lda, T p, T *res, void *stream, T cutoff)
+{
+    if (p == T(2)) return run_mat(HypNode<T>{}, m, ncols, A, lda, res, stream);
+    if (p == T(1)) return run_mat(SumNode<T>{}, m, ncols, A, lda, res, stream);
+    if (__builtin_isinf(p) || p >= cutoff) return run_mat(MaxNode<T>{}, m, ncols, A, lda, res, stream);
+    return run_mat(make_lp_node<T>(p), m, ncols, A, lda, res, stream);
 }
 
 // ---------------------------------------------------------------------------------
@@ -829,6 +894,59 @@ int vnp_snrmf_cols(int64_t m, int64_t ncols, const float *A, int64_t lda, float 
     if (ncols > 0 && !res) return -5;
     const int64_t total = ncols > 0 ? (ncols - 1) * lda + m : 0;
     return run_batched(HypNode<float>{}, SegCols{lda, m}, A, ncols, total, res, stream);
+}
+
+
+static int mat_args(int64_t m, int64_t ncols, const void *A, int64_t lda)
+{
+    if (m < 0) return -1;
+    if (ncols < 0) return -2;
+    if (m > 0 && ncols > 0 && !A) return -3;
+    if (lda < (m > 1 ? m : 1)) return -4;
+    if (m > 0 && ncols > 0 && (ncols - 1) > (VNP_MAX_N - m) / lda) return -4;
+    return 0;
+}
+
+int vnp_dnrmf_mat(int64_t m, int64_t ncols, const double *A, int64_t lda, double *res, void *stream)
+{
+    const int a = mat_args(m, ncols, A, lda);
+    if (a) return a;
+    if (!res) return -5;
+    if (m == 0 || ncols == 0) return vnp_dnrmf(0, A, 1, res, stream);
+    if (lda == m || ncols == 1) return vnp_dnrmf(m * ncols, A, 1, res, stream);
+    return run_mat(HypNode<double>{}, m, ncols, A, lda, res, stream);
+}
+
+int vnp_snrmf_mat(int64_t m, int64_t ncols, const float *A, int64_t lda, float *res, void *stream)
+{
+    const int a = mat_args(m, ncols, A, lda);
+    if (a) return a;
+    if (!res) return -5;
+    if (m == 0 || ncols == 0) return vnp_snrmf(0, A, 1, res, stream);
+    if (lda == m || ncols == 1) return vnp_snrmf(m * ncols, A, 1, res, stream);
+    return run_mat(HypNode<float>{}, m, ncols, A, lda, res, stream);
+}
+
+int vnp_dnrmp_mat(int64_t m, int64_t ncols, const double *A, int64_t lda, double p, double *res, void *stream)
+{
+    const int a = mat_args(m, ncols, A, lda);
+    if (a) return a;
+    if (!(p > 0)) return -5;
+    if (!res) return -6;
+    if (m == 0 || ncols == 0) return vnp_dnrmp(0, A, 1, p, res, stream);
+    if (lda == m || ncols == 1) return vnp_dnrmp(m * ncols, A, 1, p, res, stream);
+    return run_mat_p<double>(m, ncols, A, lda, p, res, stream, 0x1p53);
+}
+
+int vnp_snrmp_mat(int64_t m, int64_t ncols, const float *A, int64_t lda, float p, float *res, void *stream)
+{
+    const int a = mat_args(m, ncols, A, lda);
+    if (a) return a;
+    if (!(p > 0)) return -5;
+    if (!res) return -6;
+    if (m == 0 || ncols == 0) return vnp_snrmp(0, A, 1, p, res, stream);
+    if (lda == m || ncols == 1) return vnp_snrmp(m * ncols, A, 1, p, res, stream);
+    return run_mat_p<float>(m, ncols, A, lda, p, res, stream, 0x1p24f);
 }
 
 }  // extern "C"
