@@ -210,6 +210,30 @@ def nrmp(x, p: float, algo: str = "A", lanes: int | None = None, threads: int | 
     raise ValueError(algo)
 
 
+def nrmf_complex(z, incz: int = 1, n: int | None = None, threads: int | None = None):
+    """Frobenius norm of a complex vector.  |z_k|^2 = re^2 + im^2 (Sect. 1), so the norm is the
+    recursion (A) over the real view (re_0, im_0, re_1, im_1, ...) of the n logical
+    elements; element k is z[k incz] for incz >= 1, z[(n - 1 - k) |incz|] for incz <= -1."""
+    z = np.asarray(z)
+    if not np.iscomplexobj(z):
+        raise TypeError("complex input expected")
+    if incz == 0:
+        raise ValueError("incz == 0")
+    if n is None:
+        n = (z.size + abs(incz) - 1) // abs(incz) if z.size else 0
+    rdt = np.float32 if z.dtype == np.complex64 else np.float64
+    if n <= 0:
+        return rdt(0.0)
+    idx = np.arange(n) * abs(incz)
+    if incz < 0:
+        idx = idx[::-1]
+    zz = z[idx]
+    real = np.empty(2 * n, dtype=rdt)
+    real[0::2] = zz.real
+    real[1::2] = zz.imag
+    return nrmf(real, "A", threads=threads)
+
+
 def nrm_mat(a, m: int, ncols: int, lda: int, p: float = 2.0, threads: int | None = None):
     """Frobenius (p = 2) or entrywise p-norm of the m x ncols column-major array stored in a
     with leading dimension lda (Sect. 3.1): an array stored contiguously (lda == m) is one
