@@ -73,6 +73,16 @@ int vnp_snrmf(int64_t n, const float *x, int64_t incx, float *res, void *stream)
 int vnp_dnrmp(int64_t n, const double *x, int64_t incx, double p, double *res, void *stream);
 int vnp_snrmp(int64_t n, const float *x, int64_t incx, float p, float *res, void *stream);
 
+/* Frobenius norm of a complex vector (DZNRMF: double complex, SCNRMF: single complex):
+ * z holds n complex elements as (re, im) pairs, element k at z + 2 k incz for incz >= 1
+ * (BLAS reverse order for incz <= -1).  Since |z_k|^2 = re^2 + im^2 (Sect. 1), the norm
+ * is that of the real view (re_0, im_0, re_1, im_1, ...) of 2n elements, reduced by the
+ * canonical tree: for incz == 1 bitwise vnp_dnrmf / vnp_snrmf on the 2n reals, and any
+ * stride gives the bits of the contiguous copy.  Errors: n > VNP_MAX_N / 2 -> -1;
+ * z == NULL with n > 0 -> -2; incz == 0 -> -3; res == NULL -> -4. */
+int vnp_dznrmf(int64_t n, const double *z, int64_t incz, double *res, void *stream);
+int vnp_scnrmf(int64_t n, const float *z, int64_t incz, float *res, void *stream);
+
 /* ------------------------------------------------------------------------------------
  * Batched segments in one launch.  Paper: norms of the columns of a multi-dimensional
  * array, computed independently (Sect. 3.1).  x holds n_total elements; segment s is

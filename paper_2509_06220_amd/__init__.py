@@ -56,6 +56,8 @@ def lib():
             "vnp_plan_info": [vp, vp, vp, vp],
             "vnp_dnrmf_cols": [i64, i64, vp, i64, vp, vp],
             "vnp_snrmf_cols": [i64, i64, vp, i64, vp, vp],
+            "vnp_dznrmf": [i64, vp, i64, vp, vp],
+            "vnp_scnrmf": [i64, vp, i64, vp, vp],
             "vnp_dnrmf_mat": [i64, i64, vp, i64, vp, vp],
             "vnp_snrmf_mat": [i64, i64, vp, i64, vp, vp],
             "vnp_dnrmp_mat": [i64, i64, vp, i64, d, vp, vp],
@@ -241,6 +243,28 @@ def nrmf_cols(A, m, ncols, lda, out=None, stream=None):
         out = torch.empty(ncols, dtype=A.dtype, device=A.device)
     fn = "vnp_dnrmf_cols" if A.dtype == torch.float64 else "vnp_snrmf_cols"
     _check(fn, getattr(lib(), fn)(m, ncols, A.data_ptr(), lda, out.data_ptr(), _stream(A, stream)))
+    return out
+
+
+def nrmf_complex(z, n=None, incz=1, out=None, stream=None):
+    """Frobenius norm of a complex vector (torch complex128 / complex64 tensor, or its real
+    view as float64 / float32 pairs) of n elements with stride incz."""
+    import torch
+
+    if z.is_complex():
+        z = torch.view_as_real(z)
+    if not z.is_contiguous():
+        raise ValueError("the storage must be contiguous (use incz for strides)")
+    m = z.numel() // 2
+    if n is None:
+        n = (m + abs(incz) - 1) // abs(incz) if m else 0
+    if n > 0 and (n - 1) * abs(incz) + 1 > m:
+        raise ValueError("n and incz reach past the end of z")
+    d = z.dtype == torch.float64
+    if out is None:
+        out = torch.empty((), dtype=z.dtype, device=z.device)
+    fn = "vnp_dznrmf" if d else "vnp_scnrmf"
+    _check(fn, getattr(lib(), fn)(n, z.data_ptr(), incz, out.data_ptr(), _stream(z, stream)))
     return out
 
 

@@ -239,11 +239,11 @@ __global__ void __launch_bounds__(512)
         T root;
         if constexpr (GEN) {
             if (inc == 1 && (((uintptr_t)xs) % sizeof(T)) == 0)
-                root = wave_root<Node, U, true>(nd, xs, len, 1, r << lwt, ntiles, lwt, lane);
+                root = wave_root<Node, U, true>(nd, xs, len, real_stride(1), r << lwt, ntiles, lwt, lane);
             else
-                root = wave_root<Node, U, false>(nd, xs, len, inc, r << lwt, ntiles, lwt, lane);
+                root = wave_root<Node, U, false>(nd, xs, len, real_stride(inc), r << lwt, ntiles, lwt, lane);
         } else {
-            root = wave_root<Node, U, true>(nd, xs, len, 1, r << lwt, ntiles, lwt, lane);
+            root = wave_root<Node, U, true>(nd, xs, len, real_stride(1), r << lwt, ntiles, lwt, lane);
         }
         // every lane stores the same value
         if (nruns == 1)

@@ -28,7 +28,7 @@ namespace vnp {
 // ---------------------------------------------------------------------------------
 template <class Node, int U, bool FAST>
 __global__ void __launch_bounds__(1024)
-    nrm_kernel(Node nd, const typename Node::T *x, int64_t n, int64_t inc, int64_t ntiles, int lwt,
+    nrm_kernel(Node nd, const typename Node::T *x, int64_t n, Stride sd, int64_t ntiles, int lwt,
                typename Node::T *roots, typename Node::T *res)
 {
     using T = typename Node::T;
@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(1024)
     const int wpb = blockDim.x / WAVE;
     const int64_t t0 = ((int64_t)blockIdx.x * wpb + wave) << lwt;
 
-    const T r = wave_root<Node, U, FAST>(nd, x, n, inc, t0, ntiles, lwt, lane);
+    const T r = wave_root<Node, U, FAST>(nd, x, n, sd, t0, ntiles, lwt, lane);
     if (lane == 0) sbuf[wave] = r;
     lds_tree(nd, sbuf, wpb);
     if (threadIdx.x == 0) {
@@ -166,21 +166,23 @@ int release_workspaces()
 // ---------------------------------------------------------------------------------
 template <class Node>
 static void launch(const Node &nd, bool fast, dim3 grid, dim3 block, hipStream_t st, const typename Node::T *x,
-                   int64_t n, int64_t inc, int64_t ntiles, int lwt, typename Node::T *roots, typename Node::T *res)
+                   int64_t n, Stride sd, int64_t ntiles, int lwt, typename Node::T *roots, typename Node::T *res)
 {
     if (fast)
-        hipLaunchKernelGGL((nrm_kernel<Node, RowsInFlight<Node>::value, true>), grid, block, 0, st, nd, x, n, inc,
+        hipLaunchKernelGGL((nrm_kernel<Node, RowsInFlight<Node>::value, true>), grid, block, 0, st, nd, x, n, sd,
                            ntiles, lwt, roots, res);
     else
-        hipLaunchKernelGGL((nrm_kernel<Node, RowsInFlight<Node>::value, false>), grid, block, 0, st, nd, x, n, inc,
+        hipLaunchKernelGGL((nrm_kernel<Node, RowsInFlight<Node>::value, false>), grid, block, 0, st, nd, x, n, sd,
                            ntiles, lwt, roots, res);
     if (grid.x > 1)
         hipLaunchKernelGGL((nrm_finish_kernel<Node>), dim3(1), dim3(256), 0, st, nd, roots, (int64_t)grid.x, res);
 }
 
+// n logical elements, element 0 at base, address map sd; fast: contiguous and naturally
+// aligned (vector loads).
 template <class Node>
-static int run_norm(const Node &nd, int64_t n, const typename Node::T *x, int64_t incx, typename Node::T *res,
-                    void *stream)
+static int run_norm_map(const Node &nd, int64_t n, const typename Node::T *base, Stride sd, bool fast,
+                        typename Node::T *res, void *stream)
 {
     using T = typename Node::T;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -196,11 +198,29 @@ static int run_norm(const Node &nd, int64_t n, const typename Node::T *x, int64_
     Workspace *ws = nullptr;
     int rc = get_workspace(stream, sizeof(T) * (size_t)nblocks, &ws);
     if (rc) return rc;
-    const T *base = incx >= 0 ? x : x + (n - 1) * (-incx);
-    const bool fast = incx == 1 && ((uintptr_t)x % sizeof(T)) == 0;
-    launch(nd, fast, dim3((unsigned)nblocks), dim3((unsigned)(s.wpb * WAVE)), st, base, n, incx, ntiles, s.lwt,
+    launch(nd, fast, dim3((unsigned)nblocks), dim3((unsigned)(s.wpb * WAVE)), st, base, n, sd, ntiles, s.lwt,
            static_cast<T *>(ws->roots), res);
     return (int)hipGetLastError();
+}
+
+template <class Node>
+static int run_norm(const Node &nd, int64_t n, const typename Node::T *x, int64_t incx, typename Node::T *res,
+                    void *stream)
+{
+    using T = typename Node::T;
+    const T *base = incx >= 0 || n <= 0 ? x : x + (n - 1) * (-incx);
+    const bool fast = incx == 1 && ((uintptr_t)x % sizeof(T)) == 0;
+    return run_norm_map(nd, n, base, real_stride(incx), fast, res, stream);
+}
+
+// Frobenius norm of n complex elements (interleaved re, im) with stride incz (in complex
+// elements): the tree over the 2n-element real view.
+template <typename T>
+static int run_complex(int64_t n, const T *z, int64_t incz, T *res, void *stream)
+{
+    if (incz == 1) return run_norm(HypNode<T>{}, n > 0 ? 2 * n : 0, z, 1, res, stream);
+    const T *base = incz >= 0 || n <= 0 ? z : z + 2 * (n - 1) * (-incz);
+    return run_norm_map(HypNode<T>{}, n > 0 ? 2 * n : 0, base, Stride{2 * incz, 1}, false, res, stream);
 }
 
 int set_launch_shape(int wpb, int wt)
@@ -227,6 +247,24 @@ static int run_pnorm(int64_t n, const T *x, int64_t incx, T p, T *res, void *str
 using namespace vnp;
 
 extern "C" {
+
+int vnp_dznrmf(int64_t n, const double *z, int64_t incz, double *res, void *stream)
+{
+    if (n > VNP_MAX_N / 2) return -1;
+    if (n > 0 && !z) return -2;
+    if (incz == 0) return -3;
+    if (!res) return -4;
+    return run_complex<double>(n, z, incz, res, stream);
+}
+
+int vnp_scnrmf(int64_t n, const float *z, int64_t incz, float *res, void *stream)
+{
+    if (n > VNP_MAX_N / 2) return -1;
+    if (n > 0 && !z) return -2;
+    if (incz == 0) return -3;
+    if (!res) return -4;
+    return run_complex<float>(n, z, incz, res, stream);
+}
 
 int vnp_dnrmf(int64_t n, const double *x, int64_t incx, double *res, void *stream)
 {

@@ -77,11 +77,21 @@ struct LoadFast {  // contiguous, naturally aligned, full tile
     __device__ V operator()(int r, int lane) const { return __builtin_nontemporal_load(p + r * WAVE + lane); }
 };
 
+// Address map of a strided input: logical element i is x[(i >> 1) pair + (i & 1) part].
+// A real vector with stride inc has pair = 2 inc, part = inc (so element i is x[i inc]);
+// the real view (re, im, re, im, ...) of a complex vector with stride inc (in complex
+// elements) has pair = 2 inc, part = 1.
+struct Stride {
+    int64_t pair, part;
+};
+__host__ __device__ inline Stride real_stride(int64_t inc) { return Stride{2 * inc, inc}; }
+
 template <typename T>
 struct LoadGeneric {  // any stride / alignment / partial tile; zero beyond n (n >= 1)
     using V = typename Vec<T>::V;
-    const T *x;  // logical element i is x[i * inc]
-    int64_t inc, n, base;
+    const T *x;  // logical element 0
+    Stride st;
+    int64_t n, base;
     __device__ V operator()(int r, int lane) const
     {
         V v;
@@ -92,7 +102,8 @@ struct LoadGeneric {  // any stride / alignment / partial tile; zero beyond n (n
             // lane-dependent control flow precedes the wave-wide steps that follow
             const int64_t i = i0 + c;
             const bool in = i < n;
-            const T e = x[(in ? i : 0) * inc];
+            const int64_t j = in ? i : 0;
+            const T e = x[(j >> 1) * st.pair + (j & 1) * st.part];
             v[c] = in ? e : T(0);
         }
         return v;
@@ -161,7 +172,7 @@ __device__ __forceinline__ float uniform(float v)
 // groups past the end of the vector hold only zeros; they are not loaded, and the
 // partly filled group stack is combined as the zero-padded tree (node(a, 0) = a).
 template <class Node, int U>
-__device__ __noinline__ typename Node::T generic_tile_root(Node nd, const typename Node::T *x, int64_t n, int64_t inc,
+__device__ __noinline__ typename Node::T generic_tile_root(Node nd, const typename Node::T *x, int64_t n, Stride sd,
                                                            int64_t t, int lane)
 {
     using T = typename Node::T;
@@ -171,7 +182,7 @@ __device__ __noinline__ typename Node::T generic_tile_root(Node nd, const typena
     constexpr int G = ROWS / U;
     constexpr int LG = ilog2(G);
     const int64_t base = t * tile_elems<T>();
-    const LoadGeneric<T> ld{x, inc, n, base};
+    const LoadGeneric<T> ld{x, sd, n, base};
     const int64_t rows = (n - base + WAVE * C - 1) / (WAVE * C);  // rows holding elements, >= 1
     const int gn = rows >= G * U ? G : (int)((rows + U - 1) / U);  // wave-uniform
     T rstk[C][LG + 1];
@@ -224,7 +235,7 @@ constexpr int MAX_LWT = 12;  // a wave covers at most 2^12 tiles
 // across tile boundaries.  FAST: contiguous, naturally aligned input.
 template <class Node, int U, bool FAST>
 __device__ __forceinline__ typename Node::T wave_root(const Node &nd, const typename Node::T *x, int64_t n,
-                                                      int64_t inc, int64_t t0, int64_t ntiles, int lwt, int lane)
+                                                      Stride sd, int64_t t0, int64_t ntiles, int lwt, int lane)
 {
     using T = typename Node::T;
     using VV = Vec<T>;
@@ -311,13 +322,13 @@ __device__ __forceinline__ typename Node::T wave_root(const Node &nd, const type
         __builtin_amdgcn_sched_barrier(0);
         step(b, q + 1);
     };
-    auto generic = [&](int64_t t) { return LoadGeneric<T>{x, inc, n, t * TE}; };
+    auto generic = [&](int64_t t) { return LoadGeneric<T>{x, sd, n, t * TE}; };
     if constexpr (FAST) {
         const int64_t full = n / TE;  // tiles entirely inside [0, n)
         const int kfull = full <= t0 ? 0 : (full - t0 < ktiles ? (int)(full - t0) : ktiles);
         auto fast = [&](int64_t t) { return LoadFast<T>{reinterpret_cast<const typename VV::VU *>(x + t * TE)}; };
         if (kfull > 0) stream_groups(fast, 0, kfull * G);
-        if (kfull < ktiles) push_tile(uniform(generic_tile_root<Node, U>(nd, x, n, inc, t0 + kfull, lane)), kfull);
+        if (kfull < ktiles) push_tile(uniform(generic_tile_root<Node, U>(nd, x, n, sd, t0 + kfull, lane)), kfull);
     } else {
         stream_groups(generic, 0, Q);
     }
