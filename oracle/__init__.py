@@ -61,6 +61,8 @@ def _L():
             "vnpo_cr_powf": (f, [f, f]),
             "vnpo_v1_lp": (d, [d, d, d]),
             "vnpo_v1_lpf": (f, [f, f, f]),
+            "vnpo_dnrm_acc": (d, [i64, vp]),
+            "vnpo_snrm_acc": (f, [i64, vp]),
             "vnpo_dnrmf_R": (d, [i64, vp, i, i]),
             "vnpo_snrmf_R": (f, [i64, vp, i, i]),
             "vnpo_dnrmp_R": (d, [i64, vp, d, i]),
@@ -208,6 +210,16 @@ def nrmp(x, p: float, algo: str = "A", lanes: int | None = None, threads: int | 
         fn = L.vnpo_snrmp_Z if single else L.vnpo_dnrmp_Z
         return x.dtype.type(fn(n, x.ctypes.data, p, P, t))
     raise ValueError(algo)
+
+
+def nrm_acc(x):
+    """Theorem 1's algorithm: g_i = fma(x_i, x_i, g_{i-1}) in the working precision, then
+    sqrt(g_n) (no tree; its error bound grows linearly in n)."""
+    x = _prep(x)
+    L = _L()
+    if x.dtype == np.float32:
+        return np.float32(L.vnpo_snrm_acc(x.size, x.ctypes.data))
+    return np.float64(L.vnpo_dnrm_acc(x.size, x.ctypes.data))
 
 
 def nrmf_complex(z, incz: int = 1, n: int | None = None, threads: int | None = None):

@@ -565,6 +565,25 @@ static float run_R_s(node_t *nd, const float *x, int64_t stride, int64_t m, int6
 /* NaN and infinity is applied by the Python wrapper.                  */
 /* node: 0 = cr_hypot (A), 1 = v1_hypot (H).                           */
 /* ------------------------------------------------------------------ */
+/* ------------------------------------------------------------------ */
+/* Theorem 1's algorithm: one accumulator of squares updated by fma in  */
+/* the working precision, then a square root (the linear-error         */
+/* baseline the recursive algorithms are compared with, Sect. 2).      */
+/* ------------------------------------------------------------------ */
+double vnpo_dnrm_acc(int64_t n, const double *x)
+{
+    double g = 0.0;
+    for (int64_t i = 0; i < n; ++i) g = fma(x[i], x[i], g);
+    return sqrt(g);
+}
+
+float vnpo_snrm_acc(int64_t n, const float *x)
+{
+    float g = 0.0f;
+    for (int64_t i = 0; i < n; ++i) g = fmaf(x[i], x[i], g);
+    return sqrtf(g);
+}
+
 double vnpo_dnrmf_R(int64_t n, const double *x, int node, int nthreads)
 {
     node_t nd = {node == 1 ? NODE_V1 : NODE_CR, 0.0, NULL, 0};
