@@ -271,6 +271,58 @@ def served_mode(torch, vnp, vnp_gen, rates, seconds, n_payloads=4096, check=64):
     return out
 
 
+def accuracy_study(torch, vnp, vnp_gen, n_log2, seeds, np_log2, gp_log2):
+    """Synthetic analogue of the paper's accuracy study (Sect. 2 tester, Table 4): relerr
+    (Eq. (relerr), multiples of eps) against the exact norm for U(0,1) (vnp_gen, seeds 0..)
+    and N(0,1) (numpy's PCG64 standard normal, seeds 0..) inputs of n = 2^n_log2 elements,
+    for the GPU path, the oracle's A, H and Z and Theorem 1's single accumulator; and for
+    p in {1/2, 2/3, 1, sqrt 2, e, pi} (binary64, U(0,1)) the GPU (n = 2^gp_log2) and the
+    oracle's A_p (n = 2^np_log2), maximum over the seeds, against two binary128 references."""
+    import numpy as np
+
+    import oracle
+
+    n = 1 << n_log2
+    methods = ("gpu", "A", "H", "Z", "acc")
+    frob = {}
+    for dist in ("U(0,1)", "N(0,1)"):
+        for fmt in ("f64", "f32"):
+            npdt = np.float64 if fmt == "f64" else np.float32
+            errs = {m: [] for m in methods}
+            for sd in range(seeds):
+                if dist == "U(0,1)":
+                    x = vnp_gen.host_fill(n, dtype=fmt, kind="u01", seed=sd, stream=51)
+                else:
+                    x = np.random.default_rng(sd).standard_normal(n).astype(npdt)
+                ex = oracle.exact_nrm2(x)
+                vals = {"gpu": vnp.nrmf(torch.from_numpy(x).cuda()).item(), "A": oracle.nrmf(x, "A"),
+                        "H": oracle.nrmf(x, "H"), "Z": oracle.nrmf(x, "Z"), "acc": oracle.nrm_acc(x)}
+                for m in methods:
+                    errs[m].append(oracle.relerr(vals[m], ex, fmt))
+            key = f"{dist} {fmt}"
+            frob[key] = {m: {"max": round(max(v), 4), "mean": round(sum(v) / len(v), 4)} for m, v in errs.items()}
+            print(json.dumps({"frobenius": key, **frob[key]}), file=sys.stderr, flush=True)
+    # two references: the flat binary128 p-norm, and the recursion followed in binary128
+    # with the method's rounded exponents RN(p/2), RN(1/p) (the paper's kind of reference)
+    ps = {"1/2": 0.5, "2/3": 2.0 / 3.0, "1": 1.0, "sqrt2": math.sqrt(2.0), "e": math.e, "pi": math.pi}
+    pnorm = {}
+    for name, p in ps.items():
+        e = {"gpu_flat": [], "gpu_rec": [], "A_flat": [], "A_rec": []}
+        for sd in range(seeds):
+            x = vnp_gen.host_fill(1 << gp_log2, kind="u01", seed=sd, stream=61)
+            g = vnp.nrmp(torch.from_numpy(x).cuda(), p).item()
+            e["gpu_flat"].append(oracle.relerr(g, sum(oracle.ref_pnorm(x, p)), "f64"))
+            e["gpu_rec"].append(oracle.relerr(g, sum(oracle.ref_pnorm_R(x, p)), "f64"))
+            xs = x[:1 << np_log2]
+            o = oracle.nrmp(xs, p, "A")
+            e["A_flat"].append(oracle.relerr(o, sum(oracle.ref_pnorm(xs, p)), "f64"))
+            e["A_rec"].append(oracle.relerr(o, sum(oracle.ref_pnorm_R(xs, p)), "f64"))
+        pnorm[name] = {k: round(max(v), 4) for k, v in e.items()}
+        print(json.dumps({"p": name, **pnorm[name]}), file=sys.stderr, flush=True)
+    return {"n": n, "seeds": seeds, "frobenius": frob,
+            "pnorm": {"gpu_n": 1 << gp_log2, "oracle_n": 1 << np_log2, "max_relerr": pnorm}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -285,6 +337,10 @@ def main():
     ap.add_argument("--serve-rates", default="5000,20000,80000")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy 5 times (scale of the HBM byte counters)")
+    ap.add_argument("--accuracy-study", action="store_true",
+                    help="only run the synthetic accuracy study (relerr of the GPU and oracle algorithms)")
+    ap.add_argument("--study-n-log2", type=int, default=26)
+    ap.add_argument("--study-seeds", type=int, default=31)
     ap.add_argument("--profile-op", default=None,
                     help="only run one operation K times for a profiler: dnrmf, snrmf (n=2^30) or dnrmp:<p> (n=2^28)")
     args = ap.parse_args()
@@ -307,6 +363,11 @@ def main():
             vnp_gen.dev_copy(dst.data_ptr(), src.data_ptr(), nb, 0, torch.cuda.current_stream().cuda_stream)
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes": nb, "launches": 5}), flush=True)
+        return
+
+    if args.accuracy_study:
+        r = accuracy_study(torch, vnp, vnp_gen, args.study_n_log2, args.study_seeds, 18, 20)
+        print(json.dumps({"accuracy_study": r}), flush=True)
         return
 
     if args.profile_op:

@@ -76,6 +76,7 @@ def _L():
             "vnpo_sa_limbs": (i, []),
             "vnpo_sa_bias": (i, []),
             "vnpo_pnorm_quad": (None, [i64, vp, i, d, i, vp, vp]),
+            "vnpo_pnorm_R_quad": (None, [i64, vp, i, d, d, i, vp, vp]),
             "vnpo_powq2": (None, [d, d, vp, vp]),
             "vnpo_pow_ambiguous": (i64, []),
             "vnpo_pow_unresolved": (i64, []),
@@ -294,6 +295,20 @@ def ref_pnorm(x, p: float, threads: int | None = None):
     hi, lo = ctypes.c_double(), ctypes.c_double()
     _L().vnpo_pnorm_quad(x.size, x.ctypes.data, int(x.dtype == np.float32), float(p),
                          threads or default_threads(), ctypes.byref(hi), ctypes.byref(lo))
+    return hi.value, lo.value
+
+
+def ref_pnorm_R(x, p: float, threads: int | None = None):
+    """The p-norm recursion R evaluated in binary128 with the method's rounded exponents
+    RN(p/2) and RN(1/p) (binary32 roundings for binary32 input), as (hi, lo) doubles."""
+    x = _prep(x)
+    if x.dtype == np.float32:
+        hp, ip = float(np.float32(np.float32(p) * np.float32(0.5))), float(np.float32(1.0) / np.float32(p))
+    else:
+        hp, ip = p * 0.5, 1.0 / p
+    hi, lo = ctypes.c_double(), ctypes.c_double()
+    _L().vnpo_pnorm_R_quad(x.size, x.ctypes.data, int(x.dtype == np.float32), hp, ip, threads or default_threads(),
+                           ctypes.byref(hi), ctypes.byref(lo))
     return hi.value, lo.value
 
 

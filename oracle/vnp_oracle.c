@@ -822,6 +822,69 @@ void vnpo_pnorm_quad(int64_t n, const void *x, int is_single, double p, int nthr
     *lo = (double)(r - (__float128)*hi);
 }
 
+/* The p-norm recursion R with the Listing 5 node evaluated in binary128, using the
+ * method's own rounded exponents half_p = RN(p/2) and inv_p = RN(1/p) (Sect. 4 rounds
+ * them once): node(a, b) = M (1 + (m/M)^(2 half_p))^inv_p.  This is the paper's "exact"
+ * reference for p-norms (Sect. 5: the recursion followed at high precision), which keeps
+ * the effect of rounding 1/p and removes only the rounding of the node evaluations.
+ * Operands are scaled by a power of two so nothing over- or underflows; NaN/Inf follow
+ * the library contract (NaN dominates, else Inf). */
+static __float128 lpq_node(__float128 a, __float128 b, __float128 hp, __float128 ip)
+{
+    const __float128 M = a > b ? a : b, m = a > b ? b : a;
+    if (M == 0) return 0;
+    const __float128 S = powq(m / M, hp);
+    return M * powq(1 + S * S, ip);
+}
+
+/* depth < par: the two halves are evaluated as parallel tasks (same tree, any thread count) */
+static __float128 lpq_rec(const void *x, int is_single, int64_t lo, int64_t n, __float128 scale, __float128 hp,
+                          __float128 ip, int par)
+{
+    if (n == 1) {
+        const double v = is_single ? (double)((const float *)x)[lo] : ((const double *)x)[lo];
+        return fabsq((__float128)v * scale);
+    }
+    const int64_t left = (n + 1) / 2;
+    __float128 a, b;
+    if (par > 0 && n > 4096) {
+#pragma omp task shared(a)
+        a = lpq_rec(x, is_single, lo, left, scale, hp, ip, par - 1);
+        b = lpq_rec(x, is_single, lo + left, n - left, scale, hp, ip, par - 1);
+#pragma omp taskwait
+    } else {
+        a = lpq_rec(x, is_single, lo, left, scale, hp, ip, 0);
+        b = lpq_rec(x, is_single, lo + left, n - left, scale, hp, ip, 0);
+    }
+    return lpq_node(a, b, hp, ip);
+}
+
+void vnpo_pnorm_R_quad(int64_t n, const void *x, int is_single, double half_p, double inv_p, int nthreads,
+                       double *hi, double *lo)
+{
+    double amax = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double v = fabs(is_single ? (double)((const float *)x)[i] : ((const double *)x)[i]);
+        if (v > amax) amax = v;
+    }
+    *hi = 0.0;
+    *lo = 0.0;
+    if (amax == 0.0 || n <= 0) return;
+    int E;
+    frexp(amax, &E);
+    const __float128 scale = ldexpq(1.0Q, -E);
+    if (nthreads < 1) nthreads = 1;
+    int par = 0;
+    while ((1 << par) < 2 * nthreads && par < 12) ++par;
+    __float128 r = 0;
+#pragma omp parallel num_threads(nthreads)
+#pragma omp single
+    r = lpq_rec(x, is_single, 0, n, scale, (__float128)half_p, (__float128)inv_p, par);
+    r /= scale;
+    *hi = (double)r;
+    *lo = (double)(r - (__float128)*hi);
+}
+
 /* powq at binary128, for tests of the pow evaluation (returns hi + lo doubles). */
 void vnpo_powq2(double x, double y, double *hi, double *lo)
 {

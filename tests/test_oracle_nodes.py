@@ -229,3 +229,27 @@ def test_cr_pow_hard_case_goes_to_mpfr():
         assert oracle.cr_pow(x, y) == oracle.mpfr_pow(x, y)
         assert oracle.cr_powf(x, y) == np.float32(oracle.mpfr_pow(float(np.float32(x)), float(np.float32(y)), 24))
     assert oracle.counters()["pow_unresolved"] == 0
+
+
+def test_pnorm_recursion_reference_closed_forms():
+    """With exactly representable p/2 and 1/p (p = 4, 1/2, 1) the binary128 recursion equals
+    the flat binary128 p-norm; for p = 2 it is the exact Frobenius norm to binary128."""
+    rng = np.random.default_rng(11)
+    x = rng.uniform(0, 1, 3001)
+    for p in (4.0, 0.5, 1.0, 2.0):
+        hi, lo = oracle.ref_pnorm_R(x, p)
+        fh, fl = oracle.ref_pnorm(x, p)
+        assert abs((hi + lo) - (fh + fl)) <= 1e-28 * (fh + fl), p
+    hi, lo = oracle.ref_pnorm_R(x, 2.0)
+    assert hi == oracle.exact_nrm2(x)
+
+
+def test_pnorm_recursion_reference_keeps_the_exponent_rounding():
+    """For p = RN(2/3), RN(1/p) = 1.5 is not 1/p: the recursion with the method's exponents
+    differs from the flat p-norm by a bias that grows with the depth of the tree."""
+    x = np.full(1 << 12, 0.5)
+    p = 2.0 / 3.0
+    hi, lo = oracle.ref_pnorm_R(x, p)
+    fh, fl = oracle.ref_pnorm(x, p)
+    rel = abs((hi + lo) - (fh + fl)) / (fh + fl)
+    assert 2 * 2.0 ** -53 < rel < 20 * 2.0 ** -53
