@@ -107,13 +107,31 @@ __global__ void __launch_bounds__(1024)
     const int64_t k0 = (int64_t)threadIdx.x * chunk;
     const int64_t k1 = k0 + chunk < nseg ? k0 + chunk : nseg;
     int64_t sum = 0;
-    for (int64_t k = k0; k < k1; ++k) {
-        const int64_t s = order ? order[k] : k;
-        const int64_t len = seg.len(s);
-        if (len == 0) res[s] = T(0);
-        if (!seg.ok(s, n_total)) bad = 1;
-        sum += runs_of<T>(len, lwt);
+    bool any_bad = false;
+    // groups of 8 positions: all their loads are issued before any is used
+    for (int64_t kb = k0; kb < k1; kb += 8) {
+        int64_t sg[8], len[8];
+        bool ok[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t k = kb + j < k1 ? kb + j : k1 - 1;
+            sg[j] = order ? order[k] : k;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            len[j] = seg.len(sg[j]);
+            ok[j] = seg.ok(sg[j], n_total);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (kb + j < k1) {
+                if (len[j] == 0) res[sg[j]] = T(0);
+                any_bad = any_bad || !ok[j];
+                sum += runs_of<T>(len[j], lwt);
+            }
+        }
     }
+    if (any_bad) bad = 1;
     part[threadIdx.x] = sum;
     __syncthreads();
     // inclusive scan of the per-thread sums (Hillis-Steele in LDS)
@@ -124,10 +142,20 @@ __global__ void __launch_bounds__(1024)
         __syncthreads();
     }
     int64_t run = threadIdx.x == 0 ? 0 : part[threadIdx.x - 1];
-    for (int64_t k = k0; k < k1; ++k) {
-        item_off[k] = run;
-        const int64_t s = order ? order[k] : k;
-        run += runs_of<T>(seg.len(s), lwt);
+    for (int64_t kb = k0; kb < k1; kb += 8) {
+        int64_t len[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int64_t k = kb + j < k1 ? kb + j : k1 - 1;
+            len[j] = seg.len(order ? order[k] : k);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (kb + j < k1) {
+                item_off[kb + j] = run;
+                run += runs_of<T>(len[j], lwt);
+            }
+        }
     }
     __syncthreads();
     if (bad || part[blockDim.x - 1] > items_cap) {
