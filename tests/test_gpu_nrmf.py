@@ -157,3 +157,55 @@ def test_invalid_arguments():
     assert L.vnp_dnrmp(4, x.data_ptr(), 1, -1.0, x.data_ptr(), None) == -4
     assert L.vnp_dnrmp(4, x.data_ptr(), 1, float("nan"), x.data_ptr(), None) == -4
     assert L.vnp_dnrmf((1 << 40) + 1, x.data_ptr(), 1, x.data_ptr(), None) == -1
+
+
+def test_concurrent_streams_from_threads():
+    """Plain calls from four host threads on four streams (one workspace per stream): every
+    result bitwise equal to the sequential one."""
+    import threading
+
+    xs = [to_dev(vnp_gen.host_fill(n, kind="exp", lo=-20, hi=20, seed=60 + i))
+          for i, n in enumerate((1 << 20, 3 * 8192 + 5, (1 << 22) + 17, 777))]
+    ref = [gpu_norm(x) for x in xs]
+    streams = [torch.cuda.Stream() for _ in xs]
+    got = [[None] * 20 for _ in xs]
+
+    def work(i):
+        with torch.cuda.stream(streams[i]):
+            outs = [vnp.nrmf(xs[i]) for _ in range(20)]
+            streams[i].synchronize()
+            got[i] = [o.item() for o in outs]
+
+    th = [threading.Thread(target=work, args=(i,)) for i in range(len(xs))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    for i, r in enumerate(ref):
+        assert all(bits(g, "f64") == bits(r, "f64") for g in got[i]), i
+
+
+@pytest.mark.parametrize("fmt", ["f64", "f32"])
+def test_graph_capture_and_replay(fmt):
+    """A plain call captured in a HIP graph (after a warm-up call on the capture stream, so
+    its workspace exists): every replay, with new data and eager work between replays,
+    equals the eager call on the same data."""
+    dt = torch.float64 if fmt == "f64" else torch.float32
+    n = (1 << 21) + 123
+    x = torch.empty(n, dtype=dt, device="cuda")
+    out = torch.empty((), dtype=dt, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        vnp_gen.dev_fill(x, kind="exp", lo=-20, hi=20, seed=1)
+        vnp.nrmf(x, out=out)  # warm-up: creates the stream's workspace
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        vnp.nrmf(x, out=out)
+    for rep in range(5):
+        vnp_gen.dev_fill(x, kind="exp", lo=-20, hi=20, seed=100 + rep)
+        torch.cuda.synchronize()
+        eager = vnp.nrmf(x).item()  # eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        assert bits(out.item(), fmt) == bits(eager, fmt), rep
