@@ -110,6 +110,30 @@ struct LoadGeneric {  // any stride / alignment / partial tile; zero beyond n (n
     }
 };
 
+template <typename T>
+struct LoadTail {  // contiguous, naturally aligned, the last (partial) tile of the vector
+    using V = typename Vec<T>::V;
+    using VU = typename Vec<T>::VU;
+    const T *x;  // logical element 0
+    int64_t n, base;
+    __device__ V operator()(int r, int lane) const
+    {
+        constexpr int RE = WAVE * Vec<T>::N;  // elements per row
+        const int64_t r0 = base + (int64_t)r * RE;
+        if (r0 + RE <= n)  // a row inside the vector: one vector load per lane (wave-uniform test)
+            return __builtin_nontemporal_load(reinterpret_cast<const VU *>(x + r0) + lane);
+        V v;
+#pragma unroll
+        for (int c = 0; c < Vec<T>::N; ++c) {  // the partial row: branch-free, as LoadGeneric
+            const int64_t i = r0 + lane * Vec<T>::N + c;
+            const bool in = i < n;
+            const T e = x[in ? i : 0];
+            v[c] = in ? e : T(0);
+        }
+        return v;
+    }
+};
+
 // ---------------------------------------------------------------------------------
 // Subtree roots in registers.
 // ---------------------------------------------------------------------------------
@@ -167,13 +191,14 @@ __device__ __forceinline__ float uniform(float v)
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
-// Root of one tile through the generic loader (used for the partial tail tile of a
-// contiguous input, kept out of line so the vector-load loop keeps its registers).  Row
-// groups past the end of the vector hold only zeros; they are not loaded, and the
-// partly filled group stack is combined as the zero-padded tree (node(a, 0) = a).
+// Root of the partial tail tile of a contiguous, aligned input (kept out of line so the
+// vector-load loop keeps its registers): full rows by vector loads, the partial row by
+// masked loads.  Row groups past the end of the vector hold only zeros; they are not
+// loaded, and the partly filled group stack is combined as the zero-padded tree
+// (node(a, 0) = a).
 template <class Node, int U>
-__device__ __noinline__ typename Node::T generic_tile_root(Node nd, const typename Node::T *x, int64_t n, Stride sd,
-                                                           int64_t t, int lane)
+__device__ __noinline__ typename Node::T tail_tile_root(Node nd, const typename Node::T *x, int64_t n, int64_t t,
+                                                        int lane)
 {
     using T = typename Node::T;
     using VV = Vec<T>;
@@ -182,7 +207,7 @@ __device__ __noinline__ typename Node::T generic_tile_root(Node nd, const typena
     constexpr int G = ROWS / U;
     constexpr int LG = ilog2(G);
     const int64_t base = t * tile_elems<T>();
-    const LoadGeneric<T> ld{x, sd, n, base};
+    const LoadTail<T> ld{x, n, base};
     const int64_t rows = (n - base + WAVE * C - 1) / (WAVE * C);  // rows holding elements, >= 1
     const int gn = rows >= G * U ? G : (int)((rows + U - 1) / U);  // wave-uniform
     T rstk[C][LG + 1];
@@ -328,7 +353,7 @@ __device__ __forceinline__ typename Node::T wave_root(const Node &nd, const type
         const int kfull = full <= t0 ? 0 : (full - t0 < ktiles ? (int)(full - t0) : ktiles);
         auto fast = [&](int64_t t) { return LoadFast<T>{reinterpret_cast<const typename VV::VU *>(x + t * TE)}; };
         if (kfull > 0) stream_groups(fast, 0, kfull * G);
-        if (kfull < ktiles) push_tile(uniform(generic_tile_root<Node, U>(nd, x, n, sd, t0 + kfull, lane)), kfull);
+        if (kfull < ktiles) push_tile(uniform(tail_tile_root<Node, U>(nd, x, n, t0 + kfull, lane)), kfull);
     } else {
         stream_groups(generic, 0, Q);
     }
