@@ -31,8 +31,9 @@ typedef struct {
     int64_t pool_bytes;    /* device memory pool for payloads (vnp_server_alloc) */
     int max_batch;         /* most requests in one batch (>= 1) */
     int streams;           /* HIP streams = batches that may be in flight at once (>= 1) */
-    int max_wait_us;       /* a batch smaller than max_batch starts at the latest when its oldest
-                              request has waited this long; 0 = as soon as a stream is free */
+    int max_wait_us;       /* while batches are in flight, a batch smaller than max_batch starts at
+                              the latest when its oldest request has waited this long (an idle
+                              device starts at once); 0 = as soon as a stream is free */
     int inject_failure_every; /* testing: treat every k-th batch as failed (0 = never); its
                                  requests are then rerun one per batch */
 } vnp_server_config;

@@ -265,8 +265,12 @@ void vnp_server::worker_loop()
         bool go = false;
         int64_t wait_ns = -1;
         if (free_slot && !pending.empty()) {
+            // an idle device starts at once; while batches run, a small batch may wait up
+            // to max_wait_us for more requests
+            bool idle = true;
+            for (const Slot &sl : slots) idle = idle && sl.state == SlotState::Free;
             const int64_t age = now_ns() - pending.front().t_submit;
-            go = cfg.max_wait_us == 0 || (int64_t)pending.size() >= cfg.max_batch ||
+            go = idle || cfg.max_wait_us == 0 || (int64_t)pending.size() >= cfg.max_batch ||
                  age >= (int64_t)cfg.max_wait_us * 1000 || pending.front().solo;
             if (!go) wait_ns = (int64_t)cfg.max_wait_us * 1000 - age;
         }
