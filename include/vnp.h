@@ -29,6 +29,10 @@
  *     +inf; otherwise the tree result, which is +inf only if the norm overflows.
  *   - Calls on different streams may run concurrently; each (device, stream) pair gets
  *     its own workspace, created on first use and released by vnp_finalize().
+ *   - Work enqueued by a call consists of kernel launches only, so a call can be captured
+ *     in a HIP graph once its stream's workspace is large enough (after one call of the
+ *     same or a larger size on that stream; a call that must grow the workspace
+ *     allocates and synchronizes the stream).
  */
 #ifndef VNP_H
 #define VNP_H
@@ -89,7 +93,8 @@ int vnp_scnrmf(int64_t n, const float *z, int64_t incz, float *res, void *stream
  * x[offsets[s] .. offsets[s+1]) (offsets: device int64 array of nseg + 1 entries; a
  * negative length counts as empty) and its norm goes to res[s].  Each segment's result is
  * bitwise equal to the single-vector call on it.  Segments are processed in one
- * persistent launch (plus a one-block setup launch) with a per-stream workspace.
+ * persistent launch, preceded by a one-block setup launch and followed by a finish
+ * launch that reduces the run roots of long segments, with a per-stream workspace.
  * Errors: nseg < 0 -> -1; offsets == NULL -> -2; n_total < 0 or > VNP_MAX_N -> -3;
  * x == NULL -> -4; res == NULL -> -5 (p-norm: p <= 0 or NaN -> -5, res == NULL -> -6).
  * A segment reaching outside [0, n_total) is detected on the device: then every res[s]

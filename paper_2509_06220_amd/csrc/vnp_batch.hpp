@@ -40,7 +40,7 @@ int request_class_items(int dtype, const int64_t *lens, int64_t n, int64_t *item
 // Enqueues one request batch on st: a stage kernel copies the descriptor words from
 // h_src (device view of host-mapped memory; ptrs[nreq] | lens[nreq] | incs[nreq] | item
 // offsets, class c's n_c + 1 entries at 3 nreq + a_c + c) to d_desc (device, at least
-// 4 nreq + ncls words) and clears the class counters; then one batched launch per class
+// 4 nreq + ncls words); then one batched launch per class
 // writes request i of class c to res_d[a_c + i] or res_s[a_c + i], followed by a finish
 // launch for classes with requests of several runs.  ptrs are addresses of
 // logical element 0 (moved for negative strides); lengths are >= 0.
