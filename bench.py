@@ -120,11 +120,36 @@ def extra_modes(torch, vnp, vnp_gen):
     """Throughput of the other paths (informational; the headline is DNRMF)."""
     out = {}
     try:
+        # small case: n = 2^20, x = U[-1,1) (seed 0); latency of one call (kernel time by HIP
+        # events), cache-resident and after 512 MB of writes have evicted it
+        r0 = vnp_gen.recipe("c0")
+        s = torch.cuda.current_stream()
+        flush = torch.empty(1 << 26, dtype=torch.float64, device="cuda")
+        for dt, key in ((torch.float64, "c0_dnrmf"), (torch.float32, "c0_snrmf")):
+            x0 = torch.empty(r0["n"], dtype=dt, device="cuda")
+            vnp_gen.dev_fill(x0, kind=r0["kind"], seed=r0["seed"], stream=r0["stream"])
+            r = torch.empty((), dtype=dt, device="cuda")
+            _, per = time_steps(lambda: vnp.nrmf(x0, out=r), 50, 10, s, min_warm_s=0.2)
+            warm = statistics.median(per)
+            cold = []
+            for _ in range(20):
+                flush.fill_(1.0)
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(s)
+                vnp.nrmf(x0, out=r)
+                b.record(s)
+                torch.cuda.synchronize()
+                cold.append(a.elapsed_time(b))
+            nb = r0["n"] * x0.element_size()
+            out[key] = {"us_cache_resident": round(warm * 1e3, 2), "gbs_cache_resident": round(nb / warm / 1e6, 1),
+                        "us_cache_flushed": round(statistics.median(cold) * 1e3, 2),
+                        "gbs_cache_flushed": round(nb / statistics.median(cold) / 1e6, 1)}
+            del x0
+        del flush
         n = 1 << 30
         xs = torch.empty(n, dtype=torch.float32, device="cuda")
         vnp_gen.dev_fill(xs, kind="exp", lo=-20, hi=20, seed=0)
         res = torch.empty((), dtype=torch.float32, device="cuda")
-        s = torch.cuda.current_stream()
         _, per = time_steps(lambda: vnp.nrmf(xs, out=res), 10, 2, s)
         out["snrmf_gbs"] = round(n * 4 / (statistics.mean(per) / 1e3) / 1e9, 1)
         del xs

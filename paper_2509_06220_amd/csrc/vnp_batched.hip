@@ -281,6 +281,46 @@ __global__ void __launch_bounds__(512)
     }
 }
 
+// Small request batches: one block of TILE_WAVES waves per item of one tile (lwt = 0),
+// the tile reduced cooperatively (tile_root_block); results and run roots as in the
+// streaming kernel.
+template <class Node, class Seg>
+__global__ void __launch_bounds__(TILE_WAVES * WAVE)
+    batched_tile_kernel(Node nd, Seg seg, const typename Node::T *x, int64_t nseg, const int64_t *item_off,
+                        typename Node::T *roots, typename Node::T *res)
+{
+    using T = typename Node::T;
+    constexpr int64_t TE = tile_elems<T>();
+    __shared__ T part[Vec<T>::N][TILE_WAVES][WAVE];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const int64_t item = blockIdx.x;  // every thread searches the same item (block-uniform)
+    int64_t lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (item_off[mid] <= item)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int64_t k = lo, s = k;
+    const int64_t r = item - item_off[k];
+    const int64_t len = seg.len(s), inc = seg.inc(s);
+    const int64_t ntiles = (len + TE - 1) / TE;
+    const T *xs = seg.base(x, s);
+    T root;
+    if (inc == 1 && (((uintptr_t)xs) % sizeof(T)) == 0)
+        root = tile_root_block<Node, true>(nd, xs, len, real_stride(1), r, lane, w, part);
+    else
+        root = tile_root_block<Node, false>(nd, xs, len, real_stride(inc), r, lane, w, part);
+    if (w == 0 && lane == 0) {
+        if (ntiles == 1)
+            res[s] = nd.finish(root);
+        else
+            roots[item] = root;
+    }
+}
+
 // Finish kernel: one wave per segment of several runs reduces its run roots (written by
 // the streaming kernel before it on the same stream) by the fixed tree.
 template <class Node>
@@ -604,13 +644,19 @@ template <class Node>
 static void launch_class(const Node &nd, const SegList &seg, const RequestClass &k, const int64_t *item_off,
                          void *roots, typename Node::T *res, hipStream_t st)
 {
-    // one wave per item up to what is resident; blocks of one wave spread small
-    // batches over all compute units
-    const int64_t waves = std::min<int64_t>(k.items, (int64_t)cus() * 16);
-    const int wpb = waves >= 4 * (int64_t)cus() ? 4 : 1;
-    const int blocks = (int)((waves + wpb - 1) / wpb);
-    (void)launch_streaming<Node, SegList, true>(nd, seg, nullptr, k.n, nullptr, item_off, k.lwt, wpb, blocks, roots,
-                                                res, st);
+    using T = typename Node::T;
+    if (k.lwt == 0 && k.items <= 4 * (int64_t)cus()) {
+        // few tiles: one block of TILE_WAVES waves per tile
+        hipLaunchKernelGGL((batched_tile_kernel<Node, SegList>), dim3((unsigned)k.items), dim3(TILE_WAVES * WAVE), 0,
+                           st, nd, seg, (const T *)nullptr, k.n, item_off, static_cast<T *>(roots), res);
+    } else {
+        // one wave per item up to what is resident
+        const int64_t waves = std::min<int64_t>(k.items, (int64_t)cus() * 16);
+        const int wpb = waves >= 4 * (int64_t)cus() ? 4 : 1;
+        const int blocks = (int)((waves + wpb - 1) / wpb);
+        (void)launch_streaming<Node, SegList, true>(nd, seg, nullptr, k.n, nullptr, item_off, k.lwt, wpb, blocks,
+                                                    roots, res, st);
+    }
     if (k.multi) launch_finish(nd, k.n, nullptr, item_off, roots, res, st);
 }
 

@@ -61,6 +61,26 @@ __global__ void __launch_bounds__(256)
     if (threadIdx.x == 0) *res = nd.finish(root);
 }
 
+// Small vectors: one block of TILE_WAVES waves per tile (tile_root_block); the tile roots
+// go to the workspace (a grid of one tile writes the result).
+template <class Node, bool FAST>
+__global__ void __launch_bounds__(TILE_WAVES * WAVE)
+    nrm_tile_kernel(Node nd, const typename Node::T *x, int64_t n, Stride sd, typename Node::T *roots,
+                    typename Node::T *res)
+{
+    using T = typename Node::T;
+    __shared__ T part[Vec<T>::N][TILE_WAVES][WAVE];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
+    const T r = tile_root_block<Node, FAST>(nd, x, n, sd, blockIdx.x, lane, w, part);
+    if (w == 0 && lane == 0) {
+        if (gridDim.x == 1)
+            *res = nd.finish(r);
+        else
+            roots[blockIdx.x] = r;
+    }
+}
+
 template <typename T>
 __global__ void write_zero_kernel(T *res)
 {
@@ -192,6 +212,22 @@ static int run_norm_map(const Node &nd, int64_t n, const typename Node::T *base,
     }
     constexpr int64_t TE = tile_elems<T>();
     const int64_t ntiles = (n + TE - 1) / TE;
+    if (ntiles < (int64_t)cu_count() * 4 && g_force_wpb == 0 && g_force_lwt < 0) {
+        // small vector: eight waves per tile (see nrm_tile_kernel)
+        Workspace *ws = nullptr;
+        int rc = get_workspace(stream, sizeof(T) * (size_t)ntiles, &ws);
+        if (rc) return rc;
+        T *roots = static_cast<T *>(ws->roots);
+        if (fast)
+            hipLaunchKernelGGL((nrm_tile_kernel<Node, true>), dim3((unsigned)ntiles), dim3(TILE_WAVES * WAVE), 0, st,
+                               nd, base, n, sd, roots, res);
+        else
+            hipLaunchKernelGGL((nrm_tile_kernel<Node, false>), dim3((unsigned)ntiles), dim3(TILE_WAVES * WAVE), 0, st,
+                               nd, base, n, sd, roots, res);
+        if (ntiles > 1)
+            hipLaunchKernelGGL((nrm_finish_kernel<Node>), dim3(1), dim3(256), 0, st, nd, roots, ntiles, res);
+        return (int)hipGetLastError();
+    }
     const Shape s = choose_shape(ntiles);
     const int64_t per_block = (int64_t)s.wpb << s.lwt;
     const int64_t nblocks = (ntiles + per_block - 1) / per_block;

@@ -371,6 +371,68 @@ __device__ __forceinline__ typename Node::T wave_root(const Node &nd, const type
     return cur;
 }
 
+// Root of tile t by a block of TILE_WAVES waves (all waves call; contains a barrier).
+// Wave w reduces rows [8w, 8w + 8) of the tile (an aligned subtree of every lane's row
+// tree, all its loads in flight at once); the wave roots of each lane and column are
+// combined in LDS in row order, then the columns and the lanes.  The root is returned to
+// every lane of wave 0 (other waves get an unspecified value).  FAST: contiguous,
+// naturally aligned input (sd unused).
+constexpr int TILE_WAVES = 8;
+constexpr int WAVE_ROWS = ROWS / TILE_WAVES;
+
+template <class Node, bool FAST>
+__device__ __forceinline__ typename Node::T tile_root_block(
+    const Node &nd, const typename Node::T *x, int64_t n, Stride sd, int64_t t, int lane, int w,
+    typename Node::T (&part)[Vec<typename Node::T>::N][TILE_WAVES][WAVE])
+{
+    using T = typename Node::T;
+    using VV = Vec<T>;
+    using V = typename VV::V;
+    constexpr int C = VV::N;
+    constexpr int64_t TE = tile_elems<T>();
+    const int64_t base = t * TE;
+    V v[WAVE_ROWS];
+    if constexpr (FAST) {
+        if (base + TE <= n) {  // a full tile (block-uniform test)
+            const LoadFast<T> ld{reinterpret_cast<const typename VV::VU *>(x + base)};
+#pragma unroll
+            for (int r = 0; r < WAVE_ROWS; ++r) v[r] = ld(w * WAVE_ROWS + r, lane);
+        } else {
+            const LoadTail<T> ld{x, n, base};
+#pragma unroll
+            for (int r = 0; r < WAVE_ROWS; ++r) v[r] = ld(w * WAVE_ROWS + r, lane);
+        }
+    } else {
+        const LoadGeneric<T> ld{x, sd, n, base};
+#pragma unroll
+        for (int r = 0; r < WAVE_ROWS; ++r) v[r] = ld(w * WAVE_ROWS + r, lane);
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        T a[WAVE_ROWS / 2];
+#pragma unroll
+        for (int u = 0; u < WAVE_ROWS / 2; ++u) a[u] = nd.leaf(VV::get(v[2 * u], c), VV::get(v[2 * u + 1], c));
+        part[c][w][lane] = nd.node(nd.node(a[0], a[1]), nd.node(a[2], a[3]));
+    }
+    __syncthreads();
+    T col[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        T b[TILE_WAVES];
+#pragma unroll
+        for (int j = 0; j < TILE_WAVES; ++j) b[j] = part[c][j][lane];
+        col[c] = nd.node(nd.node(nd.node(b[0], b[1]), nd.node(b[2], b[3])),
+                         nd.node(nd.node(b[4], b[5]), nd.node(b[6], b[7])));
+    }
+    T r;
+    if constexpr (C == 2) {
+        r = nd.node(col[0], col[1]);
+    } else {
+        r = nd.node(nd.node(col[0], col[1]), nd.node(col[2], col[3]));
+    }
+    return lane_tree(nd, r, lane);
+}
+
 // Tree over v[0..m) (m a power of two) held in LDS, pairs at growing strides; the root
 // ends in v[0].  Call with the whole block; contains barriers.
 template <class Node, typename T>
