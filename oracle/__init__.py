@@ -223,6 +223,19 @@ def nrm_acc(x):
     return np.float64(L.vnpo_dnrm_acc(x.size, x.ctypes.data))
 
 
+def schatten(a, m: int, n: int, lda: int, p: float):
+    """Schatten p-norm of the m x n column-major matrix in a (leading dimension lda): the
+    p-norm of its singular values (Sect. 4, ||G||_{S_p} = ||s||_p).  The singular values
+    come from LAPACK (numpy.linalg.svd, a library step); the p-norm is the recursion A_p
+    (A for p = 2)."""
+    a = _prep(a)
+    if m <= 0 or n <= 0:
+        return a.dtype.type(0.0)
+    G = np.lib.stride_tricks.as_strided(a, shape=(m, n), strides=(a.itemsize, lda * a.itemsize)).copy()
+    sv = np.linalg.svd(G, compute_uv=False).astype(a.dtype)
+    return nrmf(sv, "A") if p == 2.0 else nrmp(sv, p, "A")
+
+
 def nrmf_complex(z, incz: int = 1, n: int | None = None, threads: int | None = None):
     """Frobenius norm of a complex vector.  |z_k|^2 = re^2 + im^2 (Sect. 1), so the norm is the
     recursion (A) over the real view (re_0, im_0, re_1, im_1, ...) of the n logical
