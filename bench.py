@@ -178,6 +178,13 @@ def extra_modes(torch, vnp, vnp_gen):
         _, per = time_steps(lambda: vnp.nrm_mat(A, m, ncols, lda, out=resp), 10, 2, s)
         out["dnrmf_mat_2p15x2p15_gbs"] = round(m * ncols * 8 / (statistics.mean(per) / 1e3) / 1e9, 1)
         del A
+        # Schatten 1-norm (nuclear norm) of a 1024 x 1024 FP64 matrix: the singular values
+        # (rocSOLVER) dominate the time
+        G = torch.empty(1 << 20, dtype=torch.float64, device="cuda")
+        vnp_gen.dev_fill(G, kind="u11", seed=3)
+        _, per = time_steps(lambda: vnp.schatten(G, 1024, 1024, 1024, 1.0, out=resp), 3, 1, s, min_warm_s=0.0)
+        out["dschatten_p1_1024x1024_ms"] = round(statistics.mean(per), 3)
+        del G
     except Exception as e:  # noqa: BLE001 -- report, do not hide the headline
         out["error"] = repr(e)
     return out

@@ -77,6 +77,18 @@ int vnp_snrmf(int64_t n, const float *x, int64_t incx, float *res, void *stream)
 int vnp_dnrmp(int64_t n, const double *x, int64_t incx, double p, double *res, void *stream);
 int vnp_snrmp(int64_t n, const float *x, int64_t incx, float p, float *res, void *stream);
 
+/* Schatten p-norm of a matrix (Sect. 4): with G = U S V*, the p-norm of the singular
+ * values s (p = 1 nuclear, p = 2 Frobenius, p = inf spectral norm).  G is m x n column-
+ * major at A with leading dimension lda (device, not modified).  The singular values come
+ * from rocSOLVER's gesvd on a copy of G in a per-stream workspace; their p-norm is
+ * vnp_xnrmp (vnp_xnrmf for p = 2) on the canonical tree, written to *res.  If the SVD
+ * does not converge, *res is NaN.  The call allocates on first use and may synchronize
+ * its stream when the workspace grows.  m, n, lda <= 2^31 - 1.
+ * Errors: m invalid -> -1; n invalid -> -2; A == NULL -> -3; lda < max(1, m) -> -4;
+ * p <= 0 or NaN -> -5; res == NULL -> -6. */
+int vnp_dschatten(int64_t m, int64_t n, const double *A, int64_t lda, double p, double *res, void *stream);
+int vnp_sschatten(int64_t m, int64_t n, const float *A, int64_t lda, float p, float *res, void *stream);
+
 /* Frobenius norm of a complex vector (DZNRMF: double complex, SCNRMF: single complex):
  * z holds n complex elements as (re, im) pairs, element k at z + 2 k incz for incz >= 1
  * (BLAS reverse order for incz <= -1).  Since |z_k|^2 = re^2 + im^2 (Sect. 1), the norm

@@ -56,6 +56,8 @@ def lib():
             "vnp_plan_info": [vp, vp, vp, vp],
             "vnp_dnrmf_cols": [i64, i64, vp, i64, vp, vp],
             "vnp_snrmf_cols": [i64, i64, vp, i64, vp, vp],
+            "vnp_dschatten": [i64, i64, vp, i64, d, vp, vp],
+            "vnp_sschatten": [i64, i64, vp, i64, f, vp, vp],
             "vnp_dznrmf": [i64, vp, i64, vp, vp],
             "vnp_scnrmf": [i64, vp, i64, vp, vp],
             "vnp_dnrmf_mat": [i64, i64, vp, i64, vp, vp],
@@ -243,6 +245,17 @@ def nrmf_cols(A, m, ncols, lda, out=None, stream=None):
         out = torch.empty(ncols, dtype=A.dtype, device=A.device)
     fn = "vnp_dnrmf_cols" if A.dtype == torch.float64 else "vnp_snrmf_cols"
     _check(fn, getattr(lib(), fn)(m, ncols, A.data_ptr(), lda, out.data_ptr(), _stream(A, stream)))
+    return out
+
+
+def schatten(A, m, n, lda, p, out=None, stream=None):
+    """Schatten p-norm of the column-major m x n matrix stored in A with leading dimension lda."""
+    import torch
+
+    if out is None:
+        out = torch.empty((), dtype=A.dtype, device=A.device)
+    fn = "vnp_dschatten" if A.dtype == torch.float64 else "vnp_sschatten"
+    _check(fn, getattr(lib(), fn)(m, n, A.data_ptr(), lda, float(p), out.data_ptr(), _stream(A, stream)))
     return out
 
 

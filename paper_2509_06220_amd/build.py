@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvnp.so")
-SOURCES = ["vnp_nrm.hip", "vnp_batched.hip", "vnp_server.cpp"]
+SOURCES = ["vnp_nrm.hip", "vnp_batched.hip", "vnp_server.cpp", "vnp_schatten.hip"]
 ARCH = os.environ.get("VNP_OFFLOAD_ARCH", "gfx950")
 
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-fno-fast-math", f"--offload-arch={ARCH}",
@@ -41,7 +41,8 @@ def build(verbose: bool = False) -> str:
         subprocess.check_call(cmd)
         objs.append(o)
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-L/opt/rocm/lib", "-lrocsolver",
+           "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
     for o in objs:

@@ -47,6 +47,7 @@ int request_class_items(int dtype, const int64_t *lens, int64_t n, int64_t *item
 int enqueue_request_batch(const void *h_src, void *d_desc, int64_t nreq, const RequestClass *cls, int ncls,
                           double *res_d, float *res_s, BatchWorkspace &ws, hipStream_t st);
 void release_batch_ws(BatchWorkspace &w);
+int release_svd_workspaces();
 int set_launch_shape(int wpb, int wt);
 
 }  // namespace vnp

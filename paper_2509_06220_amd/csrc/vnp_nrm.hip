@@ -362,6 +362,7 @@ const char *vnp_version(void) { return "vnp 0.1 (gfx950)"; }
 int vnp_finalize(void)
 {
     release_batch_workspaces();
+    release_svd_workspaces();
     return release_workspaces();
 }
 
