@@ -1,27 +1,28 @@
-"""Coefficients of the polynomial approximations in vnp_nodes_p.hpp.
+"""Constants of the p-node evaluation in vnp_nodes_p.hpp.
 
 Chebyshev interpolation in 60-digit arithmetic (a near-minimax fit), then rounding to
-binary64; prints each coefficient as a C hex-float literal and the largest relative error
-of the rounded polynomial, evaluated by Horner's rule in exact arithmetic, on a dense grid.
+binary64; prints each polynomial coefficient as a C hex-float literal with the largest
+error of the rounded polynomial, evaluated by Horner's rule in exact arithmetic on a dense
+grid, and writes the log2 table to vnp_lp_table.hpp.
 
     python paper_2509_06220_amd/csrc/lp_coeffs.py
 """
+import os
+
 import mpmath as mp
 
 mp.mp.dps = 60
+HERE = os.path.dirname(os.path.abspath(__file__))
+TAB_BITS = 7            # fraction bits of v in [1/2, 1) that pick the table entry
+T_MAX = mp.mpf(2) ** -8 * mp.mpf("1.01")  # |t| bound of the reduced argument, with margin
 
 
 def cheb_fit(f, a, b, deg):
     """Power-basis coefficients c[0..deg] of the degree-deg Chebyshev interpolant of f on [a, b]."""
     nodes = [(a + b) / 2 + (b - a) / 2 * mp.cos(mp.pi * (k + mp.mpf(1) / 2) / (deg + 1)) for k in range(deg + 1)]
     vals = [f(x) for x in nodes]
-    # solve the Vandermonde system in high precision (small degree, well enough conditioned here)
     A = mp.matrix([[x ** j for j in range(deg + 1)] for x in nodes])
     return list(mp.lu_solve(A, mp.matrix(vals)))
-
-
-def to_double(c):
-    return float(c)
 
 
 def horner(cs, x):
@@ -31,34 +32,56 @@ def horner(cs, x):
     return r
 
 
-def report(name, cs, f, a, b):
-    worst = mp.mpf(0)
-    for i in range(4001):
-        x = a + (b - a) * i / 4000
-        fx = f(x)
-        if fx != 0:
-            worst = max(worst, abs(horner(cs, x) - fx) / abs(fx))
-    print(f"// {name}: max relative error of the rounded polynomial {mp.nstr(worst, 3)} "
-          f"({mp.nstr(worst / mp.mpf(2) ** -53, 3)} ulp of 2^-53)")
-    for j, c in enumerate(cs):
-        print(f"    {c.hex()},  // x^{j}")
+def worst(err, a, b, npts=4000):
+    return max(err(a + (b - a) * i / npts) for i in range(npts + 1))
 
 
-# exp(x) on |x| <= ln(2) / 2, degree 11
-LN2 = mp.log(2)
-e = [to_double(c) for c in cheb_fit(mp.exp, -LN2 / 2, LN2 / 2, 11)]
-e[0] = 1.0  # exact at 0
-report("exp(x), |x| <= ln2/2, degree 11", e, mp.exp, -LN2 / 2, LN2 / 2)
-
-# log2(r) = s * g(s^2), s = (r - 1) / (r + 1), r in [sqrt(1/2), sqrt(2)]: g(u) = 2 atanh(sqrt u) / (sqrt u ln 2)
-SMAX = (mp.sqrt(2) - 1) / (mp.sqrt(2) + 1)
-
-
-def g(u):
-    if u == 0:
-        return 2 / LN2
-    return 2 * mp.atanh(mp.sqrt(u)) / (mp.sqrt(u) * LN2)
+def table():
+    """Entry j: c_j = RN(1 / mid_j), mid_j = 1/2 + (j + 1/2) / 2^(TAB_BITS+1), the centre of the
+    j-th interval of [1/2, 1); l_j = RN(log2(2 / c_j)) in [0, 1)."""
+    rows = []
+    for j in range(1 << TAB_BITS):
+        mid = mp.mpf(1) / 2 + (mp.mpf(j) + mp.mpf(1) / 2) / 2 ** (TAB_BITS + 1)
+        c = float(1 / mid)
+        rows.append((c, float(mp.log(2 / mp.mpf(c), 2))))
+        # every v of the interval has |v c_j - 1| <= T_MAX
+        lo, hi = mp.mpf(1) / 2 + mp.mpf(j) / 2 ** (TAB_BITS + 1), mp.mpf(1) / 2 + mp.mpf(j + 1) / 2 ** (TAB_BITS + 1)
+        assert max(abs(lo * mp.mpf(c) - 1), abs(hi * mp.mpf(c) - 1)) <= T_MAX
+    return rows
 
 
-gc = [to_double(c) for c in cheb_fit(g, mp.mpf(0), SMAX ** 2, 7)]
-report("2 atanh(s) / (s ln 2) as a polynomial in u = s^2, u <= 0.0295, degree 7", gc, g, mp.mpf(0), SMAX ** 2)
+def main():
+    # 2^f, |f| <= 1/2, degree 11 (exact at 0)
+    e = [float(c) for c in cheb_fit(lambda f: mp.mpf(2) ** f, mp.mpf(-0.5), mp.mpf(0.5), 11)]
+    e[0] = 1.0
+    w = worst(lambda f: abs(horner(e, f) / mp.mpf(2) ** f - 1), mp.mpf(-0.5), mp.mpf(0.5))
+    print(f"// 2^f, |f| <= 1/2, degree 11: max relative error {mp.nstr(w, 3)} (2^{mp.nstr(mp.log(w, 2), 4)})")
+    for j, c in enumerate(e):
+        print(f"    {c.hex()},  // f^{j}")
+    # log2(1 + t) = t g(t), |t| <= T_MAX, g of degree 5
+    g = [float(c) for c in cheb_fit(lambda t: mp.log(1 + t, 2) / t if t != 0 else 1 / mp.log(2), -T_MAX, T_MAX, 5)]
+    w = worst(lambda t: abs(t * horner(g, t) - mp.log(1 + t, 2)), -T_MAX, T_MAX)
+    print(f"// log2(1 + t) = t g(t), |t| <= 1.01 * 2^-8: max absolute error {mp.nstr(w, 3)} "
+          f"(2^{mp.nstr(mp.log(w, 2), 4)})")
+    for j, c in enumerate(g):
+        print(f"    {c.hex()},  // t^{j}")
+    rows = table()
+    worst_l = max(abs(mp.mpf(l) - mp.log(2 / mp.mpf(c), 2)) for c, l in rows)
+    print(f"// table: {len(rows)} entries, max |l_j - log2(2 / c_j)| = 2^{mp.nstr(mp.log(worst_l, 2), 4)}")
+    path = os.path.join(HERE, "vnp_lp_table.hpp")
+    with open(path, "w") as fh:
+        fh.write("// Table of the binary64 log2 in vnp_nodes_p.hpp, written by lp_coeffs.py (do not edit).\n")
+        fh.write(f"// Entry j (the top {TAB_BITS} fraction bits of v in [1/2, 1)): {{c_j, l_j}} with\n")
+        fh.write(f"// c_j = RN(1 / mid_j), mid_j = 1/2 + (j + 1/2) / {2 ** (TAB_BITS + 1)}, and "
+                 "l_j = RN(log2(2 / c_j)).\n")
+        fh.write("#pragma once\n\nnamespace vnp {\n\n")
+        fh.write(f"constexpr int LP_TAB_BITS = {TAB_BITS};\n")
+        fh.write(f"static __constant__ double lp_tab_src[1 << LP_TAB_BITS][2] = {{\n")
+        for c, l in rows:
+            fh.write(f"    {{{c.hex()}, {l.hex()}}},\n")
+        fh.write("};\n\n}  // namespace vnp\n")
+    print("wrote", path)
+
+
+if __name__ == "__main__":
+    main()

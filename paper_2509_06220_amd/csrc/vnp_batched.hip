@@ -225,6 +225,7 @@ __global__ void __launch_bounds__(512)
 {
     using T = typename Node::T;
     constexpr int64_t TE = tile_elems<T>();
+    node_prologue(nd);
     const int lane = threadIdx.x & (WAVE - 1);
     const int64_t total = item_off[nseg];
     const int wpb = (int)(blockDim.x / WAVE);
@@ -292,6 +293,7 @@ __global__ void __launch_bounds__(TILE_WAVES * WAVE)
     using T = typename Node::T;
     constexpr int64_t TE = tile_elems<T>();
     __shared__ T part[Vec<T>::N][TILE_WAVES][WAVE];
+    node_prologue(nd);
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int64_t item = blockIdx.x;  // every thread searches the same item (block-uniform)
@@ -328,6 +330,7 @@ __global__ void __launch_bounds__(256)
     batched_finish_kernel(Node nd, int64_t nseg, const int32_t *order, const int64_t *item_off,
                           typename Node::T *roots, typename Node::T *res)
 {
+    node_prologue(nd);
     const int lane = threadIdx.x & (WAVE - 1);
     const int wpb = (int)(blockDim.x / WAVE);
     const int64_t nwaves = (int64_t)gridDim.x * wpb;
@@ -349,6 +352,7 @@ __global__ void __launch_bounds__(256)
     values_finish_kernel(Node nd, typename Node::T *vals, int64_t count, typename Node::T *res)
 {
     __shared__ typename Node::T sbuf[256];
+    node_prologue(nd);
     const typename Node::T root = block_finish(nd, vals, count, sbuf);
     if (threadIdx.x == 0) *res = nd.finish(root);
 }

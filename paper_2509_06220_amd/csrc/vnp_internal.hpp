@@ -104,4 +104,11 @@ struct RowsInFlight<MaxNode<double>> {
     static constexpr int value = 8;
 };
 
+// Kernel-entry hook: every thread of the block calls it before the first node evaluation
+// (a node that keeps a table in LDS fills it there).  Nothing to do for these nodes.
+template <class Node>
+__device__ __forceinline__ void node_prologue(const Node &)
+{
+}
+
 }  // namespace vnp

@@ -8,101 +8,100 @@
 //
 // The two powers are evaluated as exponentials of logarithms, on the ranges the node
 // produces, without the general-purpose library routines:
-//   log2 Q = (e_m - e_M) + log2(f_m / f_M)  (frexp parts; f_m moved by a factor 2 so
-//            the ratio lies in [sqrt(1/2), sqrt(2)]; s = (f_m - f_M) / (f_m + f_M)),
+//   log2 Q = (e_m - e_M) + log2 f_m - log2 f_M   (frexp parts f in [1/2, 1), exponents e),
 //   S = 2^((p/2) log2 Q),   C = 2^((1/p) log2 Z),  Z in [1, 2].
-// log2 near 1 is s g(s^2) with s = (r - 1) / (r + 1), |s| <= 0.172, g a degree-7
-// polynomial for 2 atanh(s) / (s ln 2); 2^y splits y = k + f, |f| <= 1/2, and evaluates
-// e^(f ln 2) by a degree-11 polynomial before scaling by 2^k (coefficients: Chebyshev
-// fits printed by lp_coeffs.py).  Both keep an absolute error of a few ulps of 1 in their
-// ranges.  An absolute error d in log2 Q changes C by at most about
-// (ln 2 / 2) d relatively, whatever p is (the error of S^2 is weighted by
-// S^2 / (p (1 + S^2)) in C), so the node's relative error stays within a few eps.
+// log2 f for f in [1/2, 1): the top LP_TAB_BITS fraction bits of f pick c_j ~ 1 / f and
+// l_j = log2(2 / c_j) from a table in LDS; then log2 f = (l_j - 1) + log2(1 + t) with
+// t = fma(f, c_j, -1), |t| <= 1.01 * 2^-8, and log2(1 + t) = t g(t), g of degree 5.  No
+// division is needed.  2^y splits y = k + f, |f| <= 1/2, evaluates 2^f by a degree-11
+// polynomial in f and scales by 2^k.  (Coefficients and table: Chebyshev fits and
+// 60-digit values written by lp_coeffs.py.)
+//
+// Errors: the table values carry 2^-54 absolute, the polynomials 2^-61.7 (log2(1 + t),
+// absolute) and 2^-55.5 (2^f, relative).  An absolute error d in log2 Q changes C by at
+// most (ln 2 / 2) d relatively, whatever p is (the error of S^2 is weighted by
+// S^2 / (p (1 + S^2)) in C); one in log2 Z reaches C multiplied by ln 2 / p.
 //
 // Special operands: M is taken as the larger bit pattern, so a NaN operand becomes M and
-// the node returns NaN; an infinite M (and no NaN) returns +inf; m = 0 returns M.
+// the node returns NaN; an infinite M (and no NaN) returns +inf; m = 0 returns M.  Their
+// intermediate values are finite or NaN and are discarded by the final select.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "vnp_internal.hpp"
+#include "vnp_lp_table.hpp"
 
 namespace vnp {
 
-// q = n / d (d in [1, 4)): two Newton steps from the hardware reciprocal estimate, then one
-// correction step.
-__device__ __forceinline__ double div_near1(double n, double d)
+// The log2 table in LDS: one copy per block, filled by lp_table_fill at kernel entry.
+__device__ __forceinline__ double2 *lp_table()
 {
-    double y = __builtin_amdgcn_rcp(d);
-    double e = __builtin_fma(-d, y, 1.0);
-    y = __builtin_fma(y, e, y);
-    e = __builtin_fma(-d, y, 1.0);
-    y = __builtin_fma(y, e, y);
-    const double q = n * y;
-    return __builtin_fma(__builtin_fma(-d, q, n), y, q);
+    __shared__ double2 tab[1 << LP_TAB_BITS];
+    return tab;
 }
 
-// log2(r) = s g(s^2) for s = (r - 1) / (r + 1), r in [sqrt(1/2), sqrt(2)] (|s| <= 0.1716):
-// g(u) = 2 atanh(sqrt u) / (sqrt u ln 2), a degree-7 polynomial in u (Chebyshev fit,
-// relative error 1.4e-17; lp_coeffs.py prints the coefficients).
-__device__ __forceinline__ double log2_of_s(double s)
+// Every thread of the block calls this before the first node evaluation.
+__device__ __forceinline__ void lp_table_fill()
 {
-    const double u = s * s;
-    double t = 0x1.b592d3c48c41cp-3;
-    t = __builtin_fma(t, u, 0x1.c46e1440404d7p-3);
-    t = __builtin_fma(t, u, 0x1.0ca160627dbfcp-2);
-    t = __builtin_fma(t, u, 0x1.484afb7a67652p-2);
-    t = __builtin_fma(t, u, 0x1.a61762d693934p-2);
-    t = __builtin_fma(t, u, 0x1.2776c50ee39dcp-1);
-    t = __builtin_fma(t, u, 0x1.ec709dc3a047dp-1);
-    return __builtin_fma(s * u, t, s * 0x1.71547652b82fep+1);
+    double2 *tab = lp_table();
+    for (int i = threadIdx.x; i < (1 << LP_TAB_BITS); i += blockDim.x)
+        tab[i] = make_double2(lp_tab_src[i][0], lp_tab_src[i][1]);
+    __syncthreads();
 }
 
-// 2^y (y clamped to [-2100, 2100]: 0 and +inf beyond the binary64 range): y = k + f,
-// |f| <= 1/2, e^(f ln 2) by a degree-11 polynomial (Chebyshev fit, relative error
-// 1.7e-17), then scaled by 2^k.
-__device__ __forceinline__ double exp2_any(double y)
+// log2 f - (l_j - 1) for f in [1/2, 1), and l_j through `l`.
+__device__ __forceinline__ double log2_part(double f, double &l)
 {
-    constexpr double LN2 = 0x1.62e42fefa39efp-1;
-    y = __builtin_fmin(__builtin_fmax(y, -2100.0), 2100.0);
+    const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(f) >> 32);
+    const double2 e = lp_table()[(hi >> (20 - LP_TAB_BITS)) & ((1u << LP_TAB_BITS) - 1)];
+    l = e.y;
+    const double t = __builtin_fma(f, e.x, -1.0);
+    double g = -0x1.ec72d2e6fb6e9p-3;
+    g = __builtin_fma(g, t, 0x1.277807fe93552p-2);
+    g = __builtin_fma(g, t, -0x1.715476524c17ep-2);
+    g = __builtin_fma(g, t, 0x1.ec709dc324b6cp-2);
+    g = __builtin_fma(g, t, -0x1.71547652b82fep-1);
+    g = __builtin_fma(g, t, 0x1.71547652b82fep+0);
+    return t * g;
+}
+
+// 2^y for finite y in [-2100, 2100] (0 and +inf beyond the binary64 range).
+__device__ __forceinline__ double exp2_poly(double y)
+{
     const double k = __builtin_rint(y);
-    const double x = (y - k) * LN2;  // y - k is exact, |x| <= 0.347
-    double t = 0x1.af631d0059becp-26;
-    t = __builtin_fma(t, x, 0x1.28b4057f44145p-22);
-    t = __builtin_fma(t, x, 0x1.71ddf5749d126p-19);
-    t = __builtin_fma(t, x, 0x1.a01991ac8730ap-16);
-    t = __builtin_fma(t, x, 0x1.a01a01b14378fp-13);
-    t = __builtin_fma(t, x, 0x1.6c16c187fbe02p-10);
-    t = __builtin_fma(t, x, 0x1.111111110f225p-7);
-    t = __builtin_fma(t, x, 0x1.555555554f0cfp-5);
-    t = __builtin_fma(t, x, 0x1.555555555555ap-3);
-    t = __builtin_fma(t, x, 0x1.0000000000011p-1);
-    t = __builtin_fma(t, x, 1.0);
-    t = __builtin_fma(t, x, 1.0);
+    const double f = y - k;  // exact, |f| <= 1/2
+    double t = 0x1.e9ec1fcb69a7fp-32;
+    t = __builtin_fma(t, f, 0x1.e6228acd1c6e5p-28);
+    t = __builtin_fma(t, f, 0x1.b524ebd13a55fp-24);
+    t = __builtin_fma(t, f, 0x1.62bfc2c86d700p-20);
+    t = __builtin_fma(t, f, 0x1.ffcbfc6da6ed1p-17);
+    t = __builtin_fma(t, f, 0x1.430913112c61bp-13);
+    t = __builtin_fma(t, f, 0x1.5d87fe78a3f9cp-10);
+    t = __builtin_fma(t, f, 0x1.3b2ab6fb9f1a5p-7);
+    t = __builtin_fma(t, f, 0x1.c6b08d704a0c6p-5);
+    t = __builtin_fma(t, f, 0x1.ebfbdff82c5aep-3);
+    t = __builtin_fma(t, f, 0x1.62e42fefa39efp-1);
+    t = __builtin_fma(t, f, 1.0);
     return __builtin_amdgcn_ldexp(t, (int)k);
 }
 
 __device__ __forceinline__ double lp_core(double a, double b, double half_p, double inv_p)
 {
-    constexpr double SQRT_HALF = 0x1.6a09e667f3bcdp-1;
     const uint64_t ia = (uint64_t)__double_as_longlong(a), ib = (uint64_t)__double_as_longlong(b);
     const double M = __longlong_as_double((long long)(ia > ib ? ia : ib));
     const double m = __longlong_as_double((long long)(ia > ib ? ib : ia));
-    // log2(m / M) = (e_m - e_M) + log2(f_m / f_M), f in [1/2, 1); f_m is moved by an exact
-    // factor 2 so that f_m / f_M lies in [sqrt(1/2), sqrt(2)], where f_m - f_M is exact
-    const double fM = __builtin_amdgcn_frexp_mant(M);
-    double fm = __builtin_amdgcn_frexp_mant(m);
-    int k = __builtin_amdgcn_frexp_exp(m) - __builtin_amdgcn_frexp_exp(M);
-    const bool lo = fm < SQRT_HALF * fM, hi = fm > (2.0 * SQRT_HALF) * fM;
-    fm = lo ? 2.0 * fm : (hi ? 0.5 * fm : fm);
-    k += lo ? -1 : (hi ? 1 : 0);
-    const double lq = (double)k + log2_of_s(div_near1(fm - fM, fm + fM));
-    const double S = exp2_any(half_p * lq);
+    double lM, lm;
+    const double pM = log2_part(__builtin_amdgcn_frexp_mant(M), lM);
+    const double pm = log2_part(__builtin_amdgcn_frexp_mant(m), lm);
+    const int k = __builtin_amdgcn_frexp_exp(m) - __builtin_amdgcn_frexp_exp(M);
+    const double lq = (double)k + ((lm - lM) + (pm - pM));  // log2 Q <= 0
+    const double S = exp2_poly(__builtin_fmax(half_p * lq, -2100.0));
     const double Z = __builtin_fma(S, S, 1.0);  // in [1, 2]
-    const bool zh = Z > 2.0 * SQRT_HALF;
-    const double Zr = zh ? 0.5 * Z : Z;
-    const double lz = (zh ? 1.0 : 0.0) + log2_of_s(div_near1(Zr - 1.0, Zr + 1.0));
-    const double C = exp2_any(inv_p * lz);
+    double lZ;
+    const double pZ = log2_part(__builtin_amdgcn_frexp_mant(Z), lZ);
+    const double lz = (double)(__builtin_amdgcn_frexp_exp(Z) - 1) + (lZ + pZ);  // log2 Z in [0, 1]
+    const double C = exp2_poly(__builtin_fmin(inv_p * lz, 2100.0));
     const bool regular = m > 0.0 && M < __builtin_inf();  // also false for a NaN M
     return regular ? M * C : M;
 }
@@ -136,6 +135,14 @@ struct LpNode<float> {
 
 template <typename T>
 inline LpNode<T> make_lp_node(T p);
+
+// Kernel-entry hook of the nodes: the p node fills its log2 table (the other nodes have
+// nothing to set up).
+template <typename T>
+__device__ __forceinline__ void node_prologue(const LpNode<T> &)
+{
+    lp_table_fill();
+}
 
 template <>
 inline LpNode<double> make_lp_node<double>(double p)

@@ -33,6 +33,7 @@ __global__ void __launch_bounds__(1024)
 {
     using T = typename Node::T;
     __shared__ T sbuf[16];
+    node_prologue(nd);
     const int lane = threadIdx.x & (WAVE - 1);
     // wave index: uniform within the wave (tell the compiler, so the loops stay scalar)
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
@@ -57,6 +58,7 @@ __global__ void __launch_bounds__(256)
 {
     using T = typename Node::T;
     __shared__ T sbuf[256];
+    node_prologue(nd);
     const T root = block_finish(nd, roots, count, sbuf);
     if (threadIdx.x == 0) *res = nd.finish(root);
 }
@@ -70,6 +72,7 @@ __global__ void __launch_bounds__(TILE_WAVES * WAVE)
 {
     using T = typename Node::T;
     __shared__ T part[Vec<T>::N][TILE_WAVES][WAVE];
+    node_prologue(nd);
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const T r = tile_root_block<Node, FAST>(nd, x, n, sd, blockIdx.x, lane, w, part);
