@@ -34,6 +34,9 @@ PNODE_SOURCES = ["paper_2509_06220_amd/csrc/vnp_nrm.hip", "paper_2509_06220_amd/
                  "paper_2509_06220_amd/csrc/vnp_nodes_p.hpp", "paper_2509_06220_amd/csrc/vnp_internal.hpp"]
 VALU_FILE = os.path.join(ROOT, "profiles", "valu_fp64.json")
 FP64_PEAK_TFLOPS = 78.6
+# VALU issue rate: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 instruction per SIMD every 4 clocks
+# (16 lanes per clock; binary64 FMA, MUL, ADD and 32-bit integer operations alike)
+VALU_PEAK_TLANE_OPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def pnode_hash() -> str:
@@ -44,17 +47,17 @@ def pnode_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def pnode_flops():
-    """FP64 FLOPs per DNRMP (p = 3, n = 2^28) launch from the committed counter summary, if
-    it matches the kernel sources."""
+def pnode_counters():
+    """Counter summary of the DNRMP (p = 3, n = 2^28) launch (FP64 FLOPs, VALU instructions
+    per node, VALUBusy) from the committed profile, if it matches the kernel sources."""
     try:
         with open(VALU_FILE) as f:
             v = json.load(f)
     except (OSError, ValueError):
-        return None
+        return {}
     if v.get("kernel_sha_p") != pnode_hash():
-        return None
-    return v.get("dnrmp_3", {}).get("flops_per_launch")
+        return {}
+    return v.get("dnrmp_3", {})
 
 
 def kernel_hash() -> str:
@@ -161,12 +164,19 @@ def extra_modes(torch, vnp, vnp_gen):
             _, per = time_steps(lambda: vnp.nrmp(xp, p, out=resp), 5, 1, s)
             out[f"dnrmp_p{p:g}_gbs"] = round(n * 8 / (statistics.mean(per) / 1e3) / 1e9, 1)
             if p == 3.0:
-                fl = pnode_flops()  # the generic-p node is bound by the FP64 VALU
+                # the generic-p node is bound by VALU issue: FP64 FLOP rate against the FP64
+                # peak, and VALU instruction rate against the issue peak
+                pc = pnode_counters()
+                t_s = statistics.mean(per) / 1e3
+                fl, ipn = pc.get("flops_per_launch"), pc.get("valu_instr_per_node")
                 out["dnrmp_p3_roofline"] = {
                     "bound": "alu", "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS,
-                    "achieved": None if fl is None else round(fl / (statistics.mean(per) / 1e3) / 1e12, 2),
-                    "frac": None if fl is None else round(fl / (statistics.mean(per) / 1e3) / 1e12 / FP64_PEAK_TFLOPS, 4),
-                    "flops_per_launch": fl}
+                    "achieved": None if fl is None else round(fl / t_s / 1e12, 2),
+                    "frac": None if fl is None else round(fl / t_s / 1e12 / FP64_PEAK_TFLOPS, 4),
+                    "flops_per_launch": fl,
+                    "valu_instr_per_node": None if ipn is None else round(ipn, 1),
+                    "valu_issue_frac": None if ipn is None else round(ipn * (n - 1) / t_s / 1e12 / VALU_PEAK_TLANE_OPS, 4),
+                    "valu_busy_pct": None if not pc else round(pc.get("valu_busy_pct", 0.0), 1)}
         del xp
         torch.cuda.empty_cache()
         # norm of a 2^15 x 2^15 FP64 array stored with leading dimension 2^15 + 64 (column
