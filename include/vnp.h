@@ -79,11 +79,13 @@ int vnp_snrmp(int64_t n, const float *x, int64_t incx, float p, float *res, void
 
 /* Schatten p-norm of a matrix (Sect. 4): with G = U S V*, the p-norm of the singular
  * values s (p = 1 nuclear, p = 2 Frobenius, p = inf spectral norm).  G is m x n column-
- * major at A with leading dimension lda (device, not modified).  The singular values come
- * from rocSOLVER's gesvd on a copy of G in a per-stream workspace; their p-norm is
- * vnp_xnrmp (vnp_xnrmf for p = 2) on the canonical tree, written to *res.  If the SVD
- * does not converge, *res is NaN.  The call allocates on first use and may synchronize
- * its stream when the workspace grows.  m, n, lda <= 2^31 - 1.
+ * major at A with leading dimension lda (device, not modified).  A copy of G, scaled by a
+ * power of two, is reduced to bidiagonal form by rocSOLVER's gebrd in a per-stream
+ * workspace; the library's bisection kernel takes the singular values from the bidiagonal's
+ * Golub-Kahan form, and their p-norm is vnp_xnrmp (vnp_xnrmf for p = 2) on the canonical
+ * tree, written to *res.  A matrix with an Inf or NaN entry gives NaN.  The call allocates
+ * on first use and may synchronize its stream when the workspace grows.
+ * m, n, lda <= 2^31 - 1.
  * Errors: m invalid -> -1; n invalid -> -2; A == NULL -> -3; lda < max(1, m) -> -4;
  * p <= 0 or NaN -> -5; res == NULL -> -6. */
 int vnp_dschatten(int64_t m, int64_t n, const double *A, int64_t lda, double p, double *res, void *stream);

@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 vnp = pytest.importorskip("paper_2509_06220_amd")
 
-SHAPES = [(8, 8, 8), (37, 20, 40), (20, 37, 20), (100, 64, 128), (200, 200, 201)]
+SHAPES = [(8, 8, 8), (37, 20, 40), (20, 37, 20), (100, 64, 128), (200, 200, 201), (700, 450, 704)]
 
 
 @pytest.mark.parametrize("fmt", ["f64", "f32"])
@@ -37,6 +37,28 @@ def test_parity_against_oracle(fmt, p):
         assert abs(g - o) <= tol * o
 
 
+@pytest.mark.parametrize("p", [1.0, 2.0, 3.0, math.inf])
+def test_graded_singular_values(p):
+    """G = U diag(s) V^T with s_i from 1 down to 1e-12 (random orthogonal U, V): the GPU and
+    oracle norms agree within the same tolerance, and both within it of the norm of s."""
+    rng = np.random.default_rng(77)
+    m, n = 300, 240
+    U, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    s = np.logspace(0, -12, n)
+    G = (U * s) @ V.T
+    a = np.asfortranarray(G).reshape(-1, order="F").copy()
+    g = vnp.schatten(to_dev(a), m, n, m, p).item()
+    o = float(oracle.schatten(a, m, n, m, p))
+    exact = float(np.max(s)) if p == math.inf else float(np.sum(s ** p) ** (1.0 / p))
+    kp = n if p == 1.0 else (1.0 if p == math.inf else n ** (1.0 / p))
+    tol = (4 * kp * m + 2 * (math.ceil(math.log2(n)) + 1)) * 2.0 ** -53
+    print(f"graded p={p}: gpu {abs(g - exact) / exact:.3e}, oracle {abs(o - exact) / exact:.3e} (tol {tol:.3e})",
+          flush=True)
+    assert abs(g - o) <= tol * o
+    assert abs(g - exact) <= tol * exact
+
+
 def test_special_cases_and_errors():
     z = torch.zeros(16, dtype=torch.float64, device="cuda")
     assert vnp.schatten(z, 0, 4, 1, 2.0).item() == 0.0
@@ -53,3 +75,37 @@ def test_special_cases_and_errors():
     assert L.vnp_dschatten(4, 2, z.data_ptr(), 3, 2.0, out.data_ptr(), s) == -4
     assert L.vnp_dschatten(2, 2, z.data_ptr(), 2, -1.0, out.data_ptr(), s) == -5
     assert L.vnp_dschatten(2, 2, z.data_ptr(), 2, 2.0, None, s) == -6
+
+
+@pytest.mark.parametrize("fmt", ["f64", "f32"])
+def test_rank_deficient_scaled_and_vectors(fmt):
+    """Rank-deficient matrices (zero singular values), entries near the ends of the exponent
+    range (the off-diagonal scaling), and k = 1 (a row or a column: the Euclidean norm)."""
+    dt = np.float64 if fmt == "f64" else np.float32
+    eps = 2.0 ** -53 if fmt == "f64" else 2.0 ** -24
+    rng = np.random.default_rng(5)
+    m, n, r = 120, 90, 30
+    G = rng.standard_normal((m, r)) @ rng.standard_normal((r, n))  # rank 30
+    big, tiny = (2.0 ** 900, 2.0 ** -900) if fmt == "f64" else (2.0 ** 100, 2.0 ** -100)
+    for scale in (1.0, big, tiny):
+        a = np.asfortranarray(G * scale).reshape(-1, order="F").astype(dt)
+        for p in (1.0, 2.0, 3.0, math.inf):
+            g = vnp.schatten(to_dev(a), m, n, m, p).item()
+            o = float(oracle.schatten(a, m, n, m, p))
+            kp = n if p == 1.0 else (1.0 if p == math.inf else n ** (1.0 / p))
+            tol = (4 * kp * m + 2 * (math.ceil(math.log2(n)) + 1)) * eps
+            print(f"rank-30 {fmt} scale 2^{math.log2(scale):.0f} p={p}: rel diff {abs(g - o) / o:.3e}", flush=True)
+            assert abs(g - o) <= tol * o
+    v = rng.standard_normal(333).astype(dt)
+    want = float(oracle.nrmf(v))
+    for m_, n_ in ((333, 1), (1, 333)):
+        g = vnp.schatten(to_dev(v), m_, n_, m_, 1.0).item()
+        assert abs(g - want) <= 4 * eps * want
+
+
+def test_non_finite_entries_give_nan():
+    a = np.random.default_rng(9).standard_normal(16 * 12)
+    for bad in (np.nan, np.inf):
+        b = a.copy()
+        b[37] = bad
+        assert math.isnan(vnp.schatten(to_dev(b), 16, 12, 16, 1.0).item())
