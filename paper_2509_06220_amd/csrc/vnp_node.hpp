@@ -7,12 +7,15 @@
 //
 //   hyp_d (binary64): let M be the larger of |a|, |b|, E its biased exponent clamped to
 //   [1, 2045] and k = 1023 - E.  With a' = a 2^k, b' = b 2^k (exact),
-//       hyp_d(a, b) = 2^-k * RN(sqrt(RN(a'^2 + RN(b'^2)))),
-//   i.e. one fma for the sum of squares and a correctly rounded square root, all in
-//   a range where nothing over- or underflows.  Relative error <= (1 + eps)^2 - 1.
-//   Inputs may carry a sign (leaves); a NaN input gives NaN, otherwise an infinite
-//   input gives +inf.  hyp_d(a, 0) = |a| exactly, since RN(sqrt(RN(a'^2))) = |a'| in
-//   binary floating point -- zero padding of the tree is therefore exact.
+//       hyp_d(a, b) = 2^-k * RN(sqrt(RN(RN(a'^2) + RN(b'^2)))),
+//   i.e. two rounded squares, their rounded sum and a correctly rounded square root, all
+//   in a range where nothing over- or underflows.  Relative error <= (1 + eps)^2 - 1:
+//   the sum carries at most (1 + eps)^2 - 1, halved by the square root, and the root's
+//   own rounding adds eps.  Every operation is commutative, so hyp_d(a, b) = hyp_d(b, a)
+//   bitwise, and monotone, so the node is monotone in |a| and |b|.  Inputs may carry a
+//   sign (leaves); a NaN input gives NaN, otherwise an infinite input gives +inf.
+//   hyp_d(a, 0) = |a| exactly, since RN(sqrt(RN(a'^2))) = |a'| in binary floating point
+//   -- zero padding of the tree is therefore exact.
 //
 //   hyp_s (binary32): a^2 and b^2 are exact in binary64, so
 //       hyp_s(a, b) = RN_32(sqrt(RN_64(a^2 + b^2)) (1 + d)),  |d| < 2^-43,
@@ -61,24 +64,24 @@ __device__ __forceinline__ double hyp_d_scaled(double a, double b)
     const int k = 1023 - E;
     const double as = __builtin_amdgcn_ldexp(a, k);
     const double bs = __builtin_amdgcn_ldexp(b, k);
-    const double s = __builtin_fma(as, as, bs * bs);
+    const double s = as * as + bs * bs;
     return __builtin_amdgcn_ldexp(sqrt_cr(s), -k);
 }
 
 // The binary64 node is defined piecewise.  When the larger operand lies in
-// [2^-380, 2^500), RN(a^2 + RN(b^2)) neither overflows nor underflows and its square
+// [2^-380, 2^500), RN(RN(a^2) + RN(b^2)) neither overflows nor underflows and its square
 // root is in the range where sqrt_core is exact, so the node is
-// RN(sqrt(RN(a^2 + RN(b^2)))) computed directly; elsewhere (zeros, tiny or huge
+// RN(sqrt(RN(RN(a^2) + RN(b^2)))) computed directly; elsewhere (zeros, tiny or huge
 // operands, inf, NaN) it is the scaled form above, evaluated only for the lanes that
-// need it.  Both forms have relative error at most (1 + eps)^2 - 1 and give
-// node(a, 0) = |a|; they differ only where b^2 underflows in one form and not in the
-// other while a^2 is exactly half-way between two doubles.
+// need it.  Both forms are symmetric, have relative error at most (1 + eps)^2 - 1 and
+// give node(a, 0) = |a|; they differ only where the smaller square underflows in one
+// form and not in the other.
 __device__ __forceinline__ double hyp_d(double a, double b)
 {
     const uint32_t hm = max(hi_word(a) & 0x7fffffffu, hi_word(b) & 0x7fffffffu);
     // exponent field of the larger operand in [1023 - 380, 1023 + 500)
     const bool fast = (hm - 0x28300000u) < (0x5F300000u - 0x28300000u);
-    double r = sqrt_core(__builtin_fma(a, a, b * b));
+    double r = sqrt_core(a * a + b * b);
     // wave-uniform branch (no lane-dependent control flow), per-lane choice
     if (__builtin_amdgcn_ballot_w64(!fast) != 0) {
         const double rs = hyp_d_scaled(a, b);

@@ -82,6 +82,42 @@ def test_node_via_two_element_segments(fmt):
 
 
 @pytest.mark.parametrize("fmt", ["f64", "f32"])
+@pytest.mark.parametrize("p", [2.0, 3.0, 0.5])
+def test_node_symmetric_and_monotone(fmt, p):
+    """node(a, b) == node(b, a) bitwise, and the node is non-decreasing in each operand:
+    for fixed b, increasing |a| never lowers the value -- by one ulp for the hypot node
+    (correctly rounded operations only), over a wide sweep for every node (the p node's
+    polynomial evaluation is monotone only to within its error).  Pairs cover ratios
+    1 .. 2^-70 and the scaled ranges (tiny, huge, zero, inf)."""
+    dt = np.float64 if fmt == "f64" else np.float32
+    rng = np.random.default_rng(11)
+    k = 8192
+    lo_e, hi_e = (-1060, 1010) if fmt == "f64" else (-140, 120)
+    a = (rng.random(k) + 0.5) * np.exp2(rng.integers(lo_e, hi_e, k).astype(np.float64))
+    b = a * np.exp2(-rng.random(k) * 70)
+    a[:8], b[:8] = [0, 1, np.inf, 3, 0, 2.0 ** lo_e, 5, 1], [0, 0, 2, np.inf, 7, 2.0 ** lo_e, 5, 1]
+    a, b = a.astype(dt), b.astype(dt)
+    off = np.arange(0, 2 * k + 1, 2, dtype=np.int64)
+    doff = to_dev(off)
+
+    def node(x, y):
+        return vnp.nrm_batched(to_dev(np.stack([x, y], 1).reshape(-1)), doff, p=p).cpu().numpy()
+
+    ab, ba = node(a, -b), node(-b, a)
+    assert np.array_equal(ab.view(np.uint64 if fmt == "f64" else np.uint32),
+                          ba.view(np.uint64 if fmt == "f64" else np.uint32))
+    if p == 2.0:  # consecutive values of the first operand
+        a_up = np.nextafter(a, np.inf)
+        fin = np.isfinite(a_up)
+        assert np.all(node(a_up, b)[fin] >= ab[fin])
+    # a sweep of the first operand at a fixed second operand
+    for b0 in (1.0, 2.0 ** -30, 2.0 ** (lo_e + 20)):
+        sweep = np.sort(np.exp2(rng.uniform(lo_e, hi_e, k))).astype(dt)
+        r = node(sweep, np.full(k, b0, dt))
+        assert np.all(np.diff(r) >= 0)
+
+
+@pytest.mark.parametrize("fmt", ["f64", "f32"])
 def test_column_norms(fmt):
     m, ncols, lda = 20000, 37, 20011
     A = vnp_gen.host_fill(lda * ncols, dtype=fmt, kind="exp", lo=-10, hi=10, seed=6)
