@@ -69,6 +69,23 @@ def test_launch_shapes_are_bitwise_identical(fmt):
 
 
 @pytest.mark.parametrize("fmt", ["f64", "f32"])
+def test_one_hundred_reruns_are_bitwise_identical(fmt):
+    """100 back-to-back calls on one stream (results kept on the device, one sync at the
+    end) give the same bits, for a small vector (one block per tile) and one large enough
+    for the streaming kernel and its finish launch."""
+    for n, seed in ((1 << 20) + 7, 31), ((3 << 22) + 12345, 32):
+        x = torch.empty(n, dtype=torch.float64 if fmt == "f64" else torch.float32, device="cuda")
+        vnp_gen.dev_fill(x, kind="exp", lo=-20, hi=20, seed=seed)
+        outs = torch.empty(100, dtype=x.dtype, device="cuda")
+        for r in range(100):
+            vnp.nrmf(x, out=outs[r])
+        torch.cuda.synchronize()
+        o = outs.cpu().numpy()
+        u = o.view(np.uint64 if fmt == "f64" else np.uint32)
+        assert np.all(u == u[0]), (n, np.unique(o))
+
+
+@pytest.mark.parametrize("fmt", ["f64", "f32"])
 def test_longest_runs_per_wave(fmt):
     """Waves covering the maximum run of 2^12 tiles (all of it, and a ragged part) give
     the default shape's bits."""
