@@ -3,7 +3,8 @@
 Chebyshev interpolation in 60-digit arithmetic (a near-minimax fit), then rounding to
 binary64; prints each polynomial coefficient as a C hex-float literal with the largest
 error of the rounded polynomial, evaluated by Horner's rule in exact arithmetic on a dense
-grid, and writes the log2 table to vnp_lp_table.hpp.
+grid, and writes the tables to vnp_lp_table.hpp: the log2 table and the reduction table of
+the power Z^(1/p) (whose p-dependent values the library computes per p).
 
     python paper_2509_06220_amd/csrc/lp_coeffs.py
 """
@@ -65,6 +66,11 @@ def main():
           f"(2^{mp.nstr(mp.log(w, 2), 4)})")
     for j, c in enumerate(g):
         print(f"    {c.hex()},  // t^{j}")
+    # (1 + t)^a = 1 + t (b_1 + b_2 t + ... + b_7 t^6), |t| < 2^-7, a <= 2: the series is
+    # evaluated with the binomial coefficients of a, computed per p by the library; the
+    # first omitted term is |b_8| t^8 < 2^-56 |b_8| with |b_8| <= 1/8 for a in (0, 2]
+    bmax = max(abs(mp.binomial(mp.mpf(a) / 64, 8)) for a in range(1, 129))
+    print(f"// (1 + t)^a, |t| < 2^-7, a in (0, 2]: first omitted term <= 2^{mp.nstr(mp.log(bmax * mp.mpf(2) ** -56, 2), 4)}")
     rows = table()
     worst_l = max(abs(mp.mpf(l) - mp.log(2 / mp.mpf(c), 2)) for c, l in rows)
     print(f"// table: {len(rows)} entries, max |l_j - log2(2 / c_j)| = 2^{mp.nstr(mp.log(worst_l, 2), 4)}")
@@ -74,12 +80,22 @@ def main():
         fh.write(f"// Entry j (the top {TAB_BITS} fraction bits of v in [1/2, 1)): {{c_j, l_j}} with\n")
         fh.write(f"// c_j = RN(1 / mid_j), mid_j = 1/2 + (j + 1/2) / {2 ** (TAB_BITS + 1)}, and "
                  "l_j = RN(log2(2 / c_j)).\n")
+        fh.write(f"// Power table (Z^(1/p) for Z in [1, 2)): entry j (the top {TAB_BITS} fraction bits of Z)\n")
+        fh.write(f"// is c'_j = RN({2 ** TAB_BITS} / ({2 ** TAB_BITS} + j)), the reciprocal of the interval's left end.\n")
         fh.write("#pragma once\n\nnamespace vnp {\n\n")
         fh.write(f"constexpr int LP_TAB_BITS = {TAB_BITS};\n")
-        fh.write(f"static __constant__ double lp_tab_src[1 << LP_TAB_BITS][2] = {{\n")
+        fh.write("#define VNP_LP_LOG_TAB \\\n    { \\\n")
         for c, l in rows:
-            fh.write(f"    {{{c.hex()}, {l.hex()}}},\n")
-        fh.write("};\n\n}  // namespace vnp\n")
+            fh.write(f"        {{{c.hex()}, {l.hex()}}}, \\\n")
+        fh.write("    }\n")
+        fh.write("#define VNP_LP_POW_TAB \\\n    { \\\n")
+        for j in range(1 << TAB_BITS):
+            fh.write(f"        {float(mp.mpf(2 ** TAB_BITS) / (2 ** TAB_BITS + j)).hex()}, \\\n")
+        fh.write("    }\n")
+        fh.write("static __constant__ double lp_tab_src[1 << LP_TAB_BITS][2] = VNP_LP_LOG_TAB;\n")
+        fh.write("static __constant__ double lp_ptab_src[1 << LP_TAB_BITS] = VNP_LP_POW_TAB;\n")
+        fh.write("static const double lp_ptab_host[1 << LP_TAB_BITS] = VNP_LP_POW_TAB;\n")
+        fh.write("\n}  // namespace vnp\n")
     print("wrote", path)
 
 

@@ -111,4 +111,12 @@ __device__ __forceinline__ void node_prologue(const Node &)
 {
 }
 
+// The part of a node that device functions outside the kernel body receive (a node
+// with large per-launch tables gives a small evaluation part); these nodes are small.
+template <class Node>
+__host__ __device__ inline Node node_eval(const Node &nd)
+{
+    return nd;
+}
+
 }  // namespace vnp

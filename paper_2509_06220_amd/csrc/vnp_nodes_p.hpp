@@ -6,21 +6,28 @@
 // are rounded once and hoisted out of the recursion (Sect. 4); binary32 uses RN32(p/2)
 // and RN32(1/p) and evaluates the node in binary64, rounding the node value to binary32.
 //
-// The two powers are evaluated as exponentials of logarithms, on the ranges the node
-// produces, without the general-purpose library routines:
-//   log2 Q = (e_m - e_M) + log2 f_m - log2 f_M   (frexp parts f in [1/2, 1), exponents e),
-//   S = 2^((p/2) log2 Q),   C = 2^((1/p) log2 Z),  Z in [1, 2].
-// log2 f for f in [1/2, 1): the top LP_TAB_BITS fraction bits of f pick c_j ~ 1 / f and
-// l_j = log2(2 / c_j) from a table in LDS; then log2 f = (l_j - 1) + log2(1 + t) with
-// t = fma(f, c_j, -1), |t| <= 1.01 * 2^-8, and log2(1 + t) = t g(t), g of degree 5.  No
-// division is needed.  2^y splits y = k + f, |f| <= 1/2, evaluates 2^f by a degree-11
-// polynomial in f and scales by 2^k.  (Coefficients and table: Chebyshev fits and
-// 60-digit values written by lp_coeffs.py.)
+// The two powers are evaluated on the ranges the node produces, without the
+// general-purpose library routines and without a division:
+//   S = 2^((p/2) log2 Q),  log2 Q = (e_m - e_M) + log2 f_m - log2 f_M  (frexp parts f in
+//   [1/2, 1), exponents e).  log2 f: the top LP_TAB_BITS fraction bits of f pick c_j ~ 1/f
+//   and l_j = log2(2 / c_j) from a table in LDS; log2 f = (l_j - 1) + log2(1 + t) with
+//   t = fma(f, c_j, -1), |t| <= 1.01 * 2^-8, and log2(1 + t) = t g(t), g of degree 5.
+//   2^y splits y = k + f, |f| <= 1/2, evaluates 2^f by a degree-11 polynomial in f and
+//   scales by 2^k.
+//   C = Z^a, a = RN(1/p), Z in [1, 2]: with a = a' 2^s, a' <= 2, C = (Z^a')^(2^s).  The top
+//   LP_TAB_BITS fraction bits of Z pick c'_j = RN(2^7 / (2^7 + j)) (the reciprocal of the
+//   interval's left end), R_j = (1/c'_j)^a' and rho_j = R_j - 1 (both rounded from an
+//   extended-precision value, per p, by make_lp_node); with t = fma(Z, c'_j, -1) in
+//   [0, 2^-7), Z^a' = R_j (1 + t)^a' and (1 + t)^a' = 1 + u, u = t (b_1 + b_2 t + ... +
+//   b_7 t^6) with the binomial coefficients b_k of a'.  Then Z^a' = 1 + fma(u, R_j, rho_j):
+//   Z = 1 gives exactly 1, and R_j's rounding touches only the small product.
+// (Coefficients and tables: Chebyshev fits and 60-digit values written by lp_coeffs.py.)
 //
-// Errors: the table values carry 2^-54 absolute, the polynomials 2^-61.7 (log2(1 + t),
-// absolute) and 2^-55.5 (2^f, relative).  An absolute error d in log2 Q changes C by at
-// most (ln 2 / 2) d relatively, whatever p is (the error of S^2 is weighted by
-// S^2 / (p (1 + S^2)) in C); one in log2 Z reaches C multiplied by ln 2 / p.
+// Errors: the log2 table values carry 2^-54 absolute, the polynomials 2^-61.7
+// (log2(1 + t), absolute) and 2^-55.5 (2^f, relative); the binomial series omits less than
+// 2^-61.9.  An absolute error d in log2 Q changes C by at most (ln 2 / 2) d relatively,
+// whatever p is (the error of S^2 is weighted by S^2 / (p (1 + S^2)) in C); each squaring
+// doubles the relative error of Z^a', so p < 1/2 costs about 2^s ulps more.
 //
 // Special operands: M is taken as the larger bit pattern, so a NaN operand becomes M and
 // the node returns NaN; an infinite M (and no NaN) returns +inf; m = 0 returns M.  Their
@@ -28,25 +35,52 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <string.h>
+
+#include <cmath>
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include "vnp_internal.hpp"
 #include "vnp_lp_table.hpp"
 
 namespace vnp {
 
-// The log2 table in LDS: one copy per block, filled by lp_table_fill at kernel entry.
+constexpr int LP_TAB_N = 1 << LP_TAB_BITS;
+
+// Per-p tables of the p node (make_lp_node), passed to the kernels by value inside the
+// node and copied to LDS at kernel entry.
+struct LpTables {
+    double b[8];           // binomial coefficients b_1 .. b_7 of a' (b[7] unused)
+    double R[LP_TAB_N];    // R_j = (1/c'_j)^a', rounded
+    double rho[LP_TAB_N];  // rho_j = R_j - 1, rounded from the extended value
+};
+
+// The tables in LDS: one copy per block, filled by lp_table_fill at kernel entry.
 __device__ __forceinline__ double2 *lp_table()
 {
-    __shared__ double2 tab[1 << LP_TAB_BITS];
+    __shared__ double2 tab[LP_TAB_N];
+    return tab;
+}
+__device__ __forceinline__ double *lp_ptable()  // c'_j, R_j, rho_j, then b_1 .. b_7
+{
+    __shared__ double tab[3 * LP_TAB_N + 8];
     return tab;
 }
 
 // Every thread of the block calls this before the first node evaluation.
-__device__ __forceinline__ void lp_table_fill()
+__device__ __forceinline__ void lp_table_fill(const LpTables &k)
 {
     double2 *tab = lp_table();
-    for (int i = threadIdx.x; i < (1 << LP_TAB_BITS); i += blockDim.x)
+    double *pt = lp_ptable();
+    for (int i = threadIdx.x; i < LP_TAB_N; i += blockDim.x) {
         tab[i] = make_double2(lp_tab_src[i][0], lp_tab_src[i][1]);
+        pt[i] = lp_ptab_src[i];
+        pt[LP_TAB_N + i] = k.R[i];
+        pt[2 * LP_TAB_N + i] = k.rho[i];
+    }
+    if (threadIdx.x < 8) pt[3 * LP_TAB_N + threadIdx.x] = k.b[threadIdx.x];
     __syncthreads();
 }
 
@@ -54,7 +88,7 @@ __device__ __forceinline__ void lp_table_fill()
 __device__ __forceinline__ double log2_part(double f, double &l)
 {
     const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(f) >> 32);
-    const double2 e = lp_table()[(hi >> (20 - LP_TAB_BITS)) & ((1u << LP_TAB_BITS) - 1)];
+    const double2 e = lp_table()[(hi >> (20 - LP_TAB_BITS)) & (LP_TAB_N - 1)];
     l = e.y;
     const double t = __builtin_fma(f, e.x, -1.0);
     double g = -0x1.ec72d2e6fb6e9p-3;
@@ -86,7 +120,27 @@ __device__ __forceinline__ double exp2_poly(double y)
     return __builtin_amdgcn_ldexp(t, (int)k);
 }
 
-__device__ __forceinline__ double lp_core(double a, double b, double half_p, double inv_p)
+// Z^a for Z in [1, 2] (a = a' 2^s, see above); b: the binomial coefficients b_1 .. b_7.
+__device__ __forceinline__ double pow_z(double Z, int sq, const double *b)
+{
+    const double Zc = __builtin_fmin(Z, 0x1.fffffffffffffp0);  // Z = 2 as its predecessor: within Z's rounding
+    const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(Zc) >> 32);
+    const uint32_t j = (hi >> (20 - LP_TAB_BITS)) & (LP_TAB_N - 1);
+    const double *pt = lp_ptable();
+    const double t = __builtin_fma(Zc, pt[j], -1.0);  // in [0, 2^-7)
+    double q = b[6];
+    q = __builtin_fma(q, t, b[5]);
+    q = __builtin_fma(q, t, b[4]);
+    q = __builtin_fma(q, t, b[3]);
+    q = __builtin_fma(q, t, b[2]);
+    q = __builtin_fma(q, t, b[1]);
+    q = __builtin_fma(q, t, b[0]);
+    double C = 1.0 + __builtin_fma(t * q, pt[LP_TAB_N + j], pt[2 * LP_TAB_N + j]);
+    for (int i = 0; i < sq; ++i) C *= C;
+    return C;
+}
+
+__device__ __forceinline__ double lp_core(double a, double b, double half_p, int sq, const double *bc)
 {
     const uint64_t ia = (uint64_t)__double_as_longlong(a), ib = (uint64_t)__double_as_longlong(b);
     const double M = __longlong_as_double((long long)(ia > ib ? ia : ib));
@@ -94,67 +148,132 @@ __device__ __forceinline__ double lp_core(double a, double b, double half_p, dou
     double lM, lm;
     const double pM = log2_part(__builtin_amdgcn_frexp_mant(M), lM);
     const double pm = log2_part(__builtin_amdgcn_frexp_mant(m), lm);
-    const int k = __builtin_amdgcn_frexp_exp(m) - __builtin_amdgcn_frexp_exp(M);
-    const double lq = (double)k + ((lm - lM) + (pm - pM));  // log2 Q <= 0
+    const int e = __builtin_amdgcn_frexp_exp(m) - __builtin_amdgcn_frexp_exp(M);
+    const double lq = (double)e + ((lm - lM) + (pm - pM));  // log2 Q <= 0
     const double S = exp2_poly(__builtin_fmax(half_p * lq, -2100.0));
     const double Z = __builtin_fma(S, S, 1.0);  // in [1, 2]
-    double lZ;
-    const double pZ = log2_part(__builtin_amdgcn_frexp_mant(Z), lZ);
-    const double lz = (double)(__builtin_amdgcn_frexp_exp(Z) - 1) + (lZ + pZ);  // log2 Z in [0, 1]
-    const double C = exp2_poly(__builtin_fmin(inv_p * lz, 2100.0));
+    const double C = pow_z(Z, sq, bc);
     const bool regular = m > 0.0 && M < __builtin_inf();  // also false for a NaN M
     return regular ? M * C : M;
 }
 
+// The evaluation part of the p node: p/2 and s, with every table read from LDS.  Device
+// functions that are not inlined receive this part only (node_eval), so the tables are
+// never copied out of the kernel arguments.
 template <typename T>
-struct LpNode;
+struct LpEval;
+
+__device__ __forceinline__ const double *lp_binom_lds() { return lp_ptable() + 3 * LP_TAB_N; }
 
 template <>
-struct LpNode<double> {
+struct LpEval<double> {
     using T = double;
-    double half_p, inv_p;
+    double half_p;  // RN(p/2)
+    int sq;         // s: C = (Z^a')^(2^s)
     __device__ double leaf(double a, double b) const
     {
-        return lp_core(__builtin_fabs(a), __builtin_fabs(b), half_p, inv_p);
+        return lp_core(__builtin_fabs(a), __builtin_fabs(b), half_p, sq, lp_binom_lds());
     }
-    __device__ double node(double a, double b) const { return lp_core(a, b, half_p, inv_p); }
+    __device__ double node(double a, double b) const { return lp_core(a, b, half_p, sq, lp_binom_lds()); }
     __device__ double finish(double r) const { return r; }
 };
 
 template <>
-struct LpNode<float> {
+struct LpEval<float> {
     using T = float;
-    double half_p, inv_p;
+    double half_p;  // RN32(p/2)
+    int sq;
     __device__ float leaf(float a, float b) const
     {
-        return (float)lp_core((double)__builtin_fabsf(a), (double)__builtin_fabsf(b), half_p, inv_p);
+        return (float)lp_core((double)__builtin_fabsf(a), (double)__builtin_fabsf(b), half_p, sq, lp_binom_lds());
     }
-    __device__ float node(float a, float b) const { return (float)lp_core((double)a, (double)b, half_p, inv_p); }
+    __device__ float node(float a, float b) const
+    {
+        return (float)lp_core((double)a, (double)b, half_p, sq, lp_binom_lds());
+    }
     __device__ float finish(float r) const { return r; }
 };
+
+// The p node as the kernels receive it: the evaluation part and the per-p tables.  Its
+// own evaluation (inlined into the kernel body) takes the binomial coefficients from the
+// kernel arguments, which stay in scalar registers.
+template <typename T>
+struct LpNode : LpEval<T> {
+    LpTables tab;
+    __device__ T leaf(T a, T b) const
+    {
+        return (T)lp_core((double)__builtin_fabs((double)a), (double)__builtin_fabs((double)b), this->half_p,
+                          this->sq, tab.b);
+    }
+    __device__ T node(T a, T b) const { return (T)lp_core((double)a, (double)b, this->half_p, this->sq, tab.b); }
+    __device__ T finish(T r) const { return r; }
+};
+
+template <typename T>
+__host__ __device__ inline LpEval<T> node_eval(const LpNode<T> &nd)
+{
+    return LpEval<T>{nd.half_p, nd.sq};
+}
 
 template <typename T>
 inline LpNode<T> make_lp_node(T p);
 
-// Kernel-entry hook of the nodes: the p node fills its log2 table (the other nodes have
+// Kernel-entry hook of the nodes: the p node fills its tables (the other nodes have
 // nothing to set up).
 template <typename T>
-__device__ __forceinline__ void node_prologue(const LpNode<T> &)
+__device__ __forceinline__ void node_prologue(const LpNode<T> &nd)
 {
-    lp_table_fill();
+    lp_table_fill(nd.tab);
+}
+
+// The node for half_p = RN(p/2) and a = RN(1/p) (host side; cached, since building the
+// tables takes 2^LP_TAB_BITS extended-precision powers).
+template <typename T>
+inline LpNode<T> lp_node(double half_p, double a)
+{
+    static std::mutex mu;
+    static std::map<std::pair<uint64_t, uint64_t>, LpNode<T>> cache;
+    uint64_t kh, ka;
+    memcpy(&kh, &half_p, 8);
+    memcpy(&ka, &a, 8);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find({kh, ka});
+    if (it != cache.end()) return it->second;
+    LpNode<T> c{};
+    c.half_p = half_p;
+    c.sq = 0;
+    double ap = a;
+    while (ap > 2.0) {  // exact halvings
+        ap = std::ldexp(ap, -1);
+        ++c.sq;
+    }
+    long double bk = 1.0L;
+    for (int i = 1; i <= 7; ++i) {
+        bk = bk * ((long double)ap - (i - 1)) / i;
+        c.tab.b[i - 1] = (double)bk;
+    }
+    c.tab.b[7] = 0.0;
+    for (int j = 0; j < LP_TAB_N; ++j) {
+        const long double r = std::pow(1.0L / (long double)lp_ptab_host[j], (long double)ap);
+        c.tab.R[j] = (double)r;
+        c.tab.rho[j] = (double)(r - 1.0L);
+    }
+    if (cache.size() >= 256) cache.clear();
+    cache.emplace(std::make_pair(kh, ka), c);
+    return c;
 }
 
 template <>
 inline LpNode<double> make_lp_node<double>(double p)
 {
-    return LpNode<double>{p * 0.5, 1.0 / p};
+    return lp_node<double>(p * 0.5, 1.0 / p);
 }
 
 template <>
 inline LpNode<float> make_lp_node<float>(float p)
 {
     const float hp = p * 0.5f, ip = 1.0f / p;
-    return LpNode<float>{(double)hp, (double)ip};
+    return lp_node<float>((double)hp, (double)ip);
 }
 
 }  // namespace vnp

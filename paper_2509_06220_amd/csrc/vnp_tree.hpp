@@ -196,6 +196,7 @@ __device__ __forceinline__ float uniform(float v)
 // masked loads.  Row groups past the end of the vector hold only zeros; they are not
 // loaded, and the partly filled group stack is combined as the zero-padded tree
 // (node(a, 0) = a).
+// Not inlined, so it receives the node's evaluation part (node_eval), which is small.
 template <class Node, int U>
 __device__ __noinline__ typename Node::T tail_tile_root(Node nd, const typename Node::T *x, int64_t n, int64_t t,
                                                         int lane)
@@ -353,7 +354,9 @@ __device__ __forceinline__ typename Node::T wave_root(const Node &nd, const type
         const int kfull = full <= t0 ? 0 : (full - t0 < ktiles ? (int)(full - t0) : ktiles);
         auto fast = [&](int64_t t) { return LoadFast<T>{reinterpret_cast<const typename VV::VU *>(x + t * TE)}; };
         if (kfull > 0) stream_groups(fast, 0, kfull * G);
-        if (kfull < ktiles) push_tile(uniform(tail_tile_root<Node, U>(nd, x, n, t0 + kfull, lane)), kfull);
+        if (kfull < ktiles)
+            push_tile(uniform(tail_tile_root<decltype(node_eval(nd)), U>(node_eval(nd), x, n, t0 + kfull, lane)),
+                      kfull);
     } else {
         stream_groups(generic, 0, Q);
     }

@@ -66,7 +66,7 @@ def test_pnorm_strides_and_specials(fmt):
 
 
 @pytest.mark.parametrize("fmt", ["f64", "f32"])
-@pytest.mark.parametrize("p", [0.5, 1.5, 3.0, 4.5, 8.0, 100.0])
+@pytest.mark.parametrize("p", [0.25, 0.3, 0.5, 0.75, 1.5, 3.0, 4.5, 8.0, 100.0])
 def test_pnode_accuracy(fmt, p):
     """The device p node on 4096 pairs spanning magnitude ratios 1 .. 2^-80 (as two-element
     segments, so each result is one leaf node) against the binary128 reference and the
