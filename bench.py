@@ -341,6 +341,7 @@ def accuracy_study(torch, vnp, vnp_gen, n_log2, seeds, np_log2, gp_log2):
                         "H": oracle.nrmf(x, "H"), "Z": oracle.nrmf(x, "Z"), "acc": oracle.nrm_acc(x)}
                 for m in methods:
                     errs[m].append(oracle.relerr(vals[m], ex, fmt))
+                print(f"accuracy study: {dist} {fmt} seed {sd} done", file=sys.stderr, flush=True)
             key = f"{dist} {fmt}"
             frob[key] = {m: {"max": round(max(v), 4), "mean": round(sum(v) / len(v), 4)} for m, v in errs.items()}
             print(json.dumps({"frobenius": key, **frob[key]}), file=sys.stderr, flush=True)
