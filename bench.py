@@ -480,7 +480,9 @@ def main():
                    "n": n, "incx": 1, "tree_id": hex(vnp.tree_id(0))},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": tr,
-                     "kernel_ms_mean": round(kern_ms, 4), "kernel_ms_min": round(min(per), 4),
+                     "kernel_ms_mean": round(kern_ms, 4), "kernel_ms_median": round(statistics.median(per), 4),
+                     "kernel_ms_min": round(min(per), 4), "kernel_ms_max": round(max(per), 4),
+                     "kernel_launches_timed": len(per),
                      "algorithmic_bytes": nbytes, "plain_read_gbs": round(read_gbs, 1)},
         "result": res.item(),
     }
