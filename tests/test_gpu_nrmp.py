@@ -101,3 +101,46 @@ def test_pnode_accuracy(fmt, p):
     bound = 4.0 * max(1.0, 1.0 / p) if fmt == "f64" else 1.1 + math.log(2.0) / p
     assert worst_ref <= bound, (worst_ref, bound)
     assert worst_or <= 2 * bound + 1, (worst_or, bound)
+
+
+@pytest.mark.parametrize("fmt", ["f64", "f32"])
+def test_graph_capture_of_the_p_node(fmt):
+    """The p node's per-p tables travel in the kernel arguments, so a captured call keeps
+    them: every replay of a captured DNRMP (streaming and finish kernels, a ragged tail
+    tile) equals the eager call, with calls at other p in between."""
+    dt = torch.float64 if fmt == "f64" else torch.float32
+    n = (1 << 21) + 321
+    x = torch.empty(n, dtype=dt, device="cuda")
+    out = torch.empty((), dtype=dt, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        vnp_gen.dev_fill(x, kind="exp", lo=-10, hi=10, seed=3)
+        vnp.nrmp(x, 3.0, out=out)  # warm-up: the stream's workspace
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        vnp.nrmp(x, 3.0, out=out)
+    for rep in range(4):
+        vnp_gen.dev_fill(x, kind="exp", lo=-10, hi=10, seed=200 + rep)
+        torch.cuda.synchronize()
+        other = vnp.nrmp(x, 1.5 + rep).item()  # another p, eagerly, between replays
+        eager = vnp.nrmp(x, 3.0).item()
+        g.replay()
+        torch.cuda.synchronize()
+        assert out.item() == eager, rep
+        assert other != eager
+
+
+def test_many_distinct_p():
+    """More distinct p values than the host keeps tables for (the cache is cleared and
+    refilled): each result stays within the parity bar of the oracle's A_p."""
+    rng = np.random.default_rng(17)
+    x = vnp_gen.host_fill(3000, dtype="f64", kind="exp", lo=-5, hi=5, seed=9, stream=3)
+    d = to_dev(x)
+    for p in np.concatenate([rng.uniform(0.5, 20.0, 290), [0.5, 7.0]]):
+        p = float(p)
+        if p in (1.0, 2.0):
+            continue
+        g = gpu_p(d, p)
+        o = float(oracle.nrmp(x, p, "A"))
+        assert_parity(g, o, 3000, "f64")
