@@ -116,7 +116,44 @@ def cpu_baseline(n_sample: int):
     dt = time.perf_counter() - t0
     return {"value": round(n_sample * 8 / dt / 1e9, 4), "unit": "GB/s", "cores": threads, "kind": "oracle",
             "sample": f"first 2^{int(np.log2(n_sample))} elements of the n=2^30 vector, "
-                      f"O-A (R with correctly rounded hypot), {threads} threads, {dt:.2f} s"}
+                      f"O-A (R with correctly rounded hypot), {threads} threads, {dt:.2f} s"}, x
+
+
+def oracle_timings(x_c1):
+    """The oracle's recursions A and H timed on the host, single-threaded and on all the
+    threads it uses: C0 (n = 2^20, U[-1,1), seed 0) and, all threads only, the C1 vector
+    (x_c1, 2^30 elements); with the CPU model and core count (informational)."""
+    import os
+
+    import oracle
+    import vnp_gen
+
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    threads = oracle.default_threads()
+    r0 = vnp_gen.recipe("c0")
+    x0 = vnp_gen.host_fill(r0["n"], kind=r0["kind"], seed=r0["seed"], stream=r0["stream"])
+    out = {"cpu_model": model, "nproc": os.cpu_count(), "threads": threads, "runs": {}}
+
+    def run(tag, x, method, th):
+        oracle.nrmf(x[:4096], method, threads=th)
+        t0 = time.perf_counter()
+        oracle.nrmf(x, method, threads=th)
+        dt = time.perf_counter() - t0
+        out["runs"][tag] = {"s": round(dt, 4), "GB/s": round(x.size * 8 / dt / 1e9, 4)}
+
+    for method in ("A", "H"):
+        run(f"C0 O-{method} 1 thread", x0, method, 1)
+        run(f"C0 O-{method} {threads} threads", x0, method, threads)
+    run(f"C1 O-H {threads} threads", x_c1, "H", threads)
+    return out
 
 
 def extra_modes(torch, vnp, vnp_gen):
@@ -504,7 +541,9 @@ def main():
         except Exception as e:  # noqa: BLE001
             line["served"] = {"error": repr(e)}
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(1 << args.cpu_sample_log2)
+        line["cpu_baseline"], xc = cpu_baseline(1 << args.cpu_sample_log2)
+        line["oracle_timings"] = oracle_timings(xc)
+        del xc
     print(json.dumps(line), flush=True)
 
 
