@@ -227,8 +227,11 @@ static int run_norm_map(const Node &nd, int64_t n, const typename Node::T *base,
         else
             hipLaunchKernelGGL((nrm_tile_kernel<Node, false>), dim3((unsigned)ntiles), dim3(TILE_WAVES * WAVE), 0, st,
                                nd, base, n, sd, roots, res);
+        // the finish: one wave while the roots fit one pass of it (no cross-wave barriers);
+        // every power-of-two width evaluates the same tree
         if (ntiles > 1)
-            hipLaunchKernelGGL((nrm_finish_kernel<Node>), dim3(1), dim3(256), 0, st, nd, roots, ntiles, res);
+            hipLaunchKernelGGL((nrm_finish_kernel<Node>), dim3(1), dim3(ntiles <= 8 * WAVE ? WAVE : 256), 0, st, nd,
+                               roots, ntiles, res);
         return (int)hipGetLastError();
     }
     const Shape s = choose_shape(ntiles);
