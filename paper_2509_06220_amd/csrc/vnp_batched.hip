@@ -108,6 +108,9 @@ __global__ void __launch_bounds__(1024)
     const int64_t k1 = k0 + chunk < nseg ? k0 + chunk : nseg;
     int64_t sum = 0;
     bool any_bad = false;
+    // a thread of at most 8 positions keeps their lengths for the second pass
+    const bool one_group = k1 - k0 <= 8;
+    int64_t kept[8];
     // groups of 8 positions: all their loads are issued before any is used
     for (int64_t kb = k0; kb < k1; kb += 8) {
         int64_t sg[8], len[8];
@@ -121,6 +124,7 @@ __global__ void __launch_bounds__(1024)
         for (int j = 0; j < 8; ++j) {
             len[j] = seg.len(sg[j]);
             ok[j] = seg.ok(sg[j], n_total);
+            kept[j] = len[j];
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -146,8 +150,12 @@ __global__ void __launch_bounds__(1024)
         int64_t len[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const int64_t k = kb + j < k1 ? kb + j : k1 - 1;
-            len[j] = seg.len(order ? order[k] : k);
+            if (one_group) {
+                len[j] = kept[j];
+            } else {
+                const int64_t k = kb + j < k1 ? kb + j : k1 - 1;
+                len[j] = seg.len(order ? order[k] : k);
+            }
         }
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
