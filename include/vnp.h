@@ -32,7 +32,10 @@
  *   - Work enqueued by a call consists of kernel launches only, so a call can be captured
  *     in a HIP graph once its stream's workspace is large enough (after one call of the
  *     same or a larger size on that stream; a call that must grow the workspace
- *     allocates and synchronizes the stream).
+ *     allocates and synchronizes the stream).  A p-norm with a p other than 1, 2 or
+ *     inf also needs its p's constant table on the device, which the first call with
+ *     that p (on that device) builds and uploads with a synchronous copy; it is kept
+ *     until vnp_finalize().
  */
 #ifndef VNP_H
 #define VNP_H
@@ -184,8 +187,8 @@ const char *vnp_version(void);
 uint32_t vnp_tree_id(int dtype);
 /* Elements per tile of the canonical tree for a dtype. */
 int64_t vnp_tile_elems(int dtype);
-/* Release per-stream workspaces of the current device.  Not thread-safe with calls
- * in flight. */
+/* Release the current device's per-stream workspaces and p-norm tables.  Not
+ * thread-safe with calls in flight. */
 int vnp_finalize(void);
 
 /* Launch-shape override for tests and tuning: waves per block and tiles per wave

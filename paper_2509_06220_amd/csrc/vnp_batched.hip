@@ -576,7 +576,9 @@ static int run_batched_p(const Seg &seg, const T *x, int64_t nseg, int64_t total
     if (p == T(2)) return run_batched(HypNode<T>{}, seg, x, nseg, total, res, stream);
     if (p == T(1)) return run_batched(SumNode<T>{}, seg, x, nseg, total, res, stream);
     if (__builtin_isinf(p) || p >= cutoff) return run_batched(MaxNode<T>{}, seg, x, nseg, total, res, stream);
-    return run_batched(make_lp_node<T>(p), seg, x, nseg, total, res, stream);
+    LpNode<T> nd;
+    const int rc = make_lp_node<T>(p, &nd);
+    return rc ? rc : run_batched(nd, seg, x, nseg, total, res, stream);
 }
 
 // Norm of an m x ncols array with leading dimension lda > m (Sect. 3.1): column norms
@@ -611,7 +613,9 @@ static int run_mat_p(int64_t m, int64_t ncols, const T *A, int64_t lda, T p, T *
     if (p == T(2)) return run_mat(HypNode<T>{}, m, ncols, A, lda, res, stream);
     if (p == T(1)) return run_mat(SumNode<T>{}, m, ncols, A, lda, res, stream);
     if (__builtin_isinf(p) || p >= cutoff) return run_mat(MaxNode<T>{}, m, ncols, A, lda, res, stream);
-    return run_mat(make_lp_node<T>(p), m, ncols, A, lda, res, stream);
+    LpNode<T> nd;
+    const int rc = make_lp_node<T>(p, &nd);
+    return rc ? rc : run_mat(nd, m, ncols, A, lda, res, stream);
 }
 
 // ---------------------------------------------------------------------------------
@@ -673,18 +677,23 @@ static void launch_class(const Node &nd, const SegList &seg, const RequestClass 
 }
 
 template <typename T>
-static void launch_class_p(const SegList &seg, const RequestClass &k, const int64_t *item_off, void *roots, T *res,
-                           T cutoff, hipStream_t st)
+static int launch_class_p(const SegList &seg, const RequestClass &k, const int64_t *item_off, void *roots, T *res,
+                          T cutoff, hipStream_t st)
 {
     const T pt = (T)k.p;
-    if (pt == T(2))
+    if (pt == T(2)) {
         launch_class(HypNode<T>{}, seg, k, item_off, roots, res, st);
-    else if (pt == T(1))
+    } else if (pt == T(1)) {
         launch_class(SumNode<T>{}, seg, k, item_off, roots, res, st);
-    else if (__builtin_isinf(pt) || pt >= cutoff)
+    } else if (__builtin_isinf(pt) || pt >= cutoff) {
         launch_class(MaxNode<T>{}, seg, k, item_off, roots, res, st);
-    else
-        launch_class(make_lp_node<T>(pt), seg, k, item_off, roots, res, st);
+    } else {
+        LpNode<T> nd;
+        const int rc = make_lp_node<T>(pt, &nd);
+        if (rc) return rc;
+        launch_class(nd, seg, k, item_off, roots, res, st);
+    }
+    return 0;
 }
 
 int enqueue_request_batch(const void *h_src, void *d_desc, int64_t nreq, const RequestClass *cls, int ncls,
@@ -707,10 +716,9 @@ int enqueue_request_batch(const void *h_src, void *d_desc, int64_t nreq, const R
         const SegList seg{ptrs + k.a, w + nreq + k.a, w + 2 * nreq + k.a};
         const int64_t *item_off = w + 3 * nreq + k.a + c;
         void *rt = static_cast<char *>(ws.roots) + 8 * roots_off;
-        if (k.dtype == VNP_F32)
-            launch_class_p<float>(seg, k, item_off, rt, res_s + k.a, 0x1p24f, st);
-        else
-            launch_class_p<double>(seg, k, item_off, rt, res_d + k.a, 0x1p53, st);
+        rc = k.dtype == VNP_F32 ? launch_class_p<float>(seg, k, item_off, rt, res_s + k.a, 0x1p24f, st)
+                                : launch_class_p<double>(seg, k, item_off, rt, res_d + k.a, 0x1p53, st);
+        if (rc) return rc;
         roots_off += k.items;
     }
     return (int)hipGetLastError();
@@ -750,7 +758,9 @@ static int plan_enqueue_p(PlanImpl &P, const BatchShape &sh, hipStream_t st, T c
     if (p == T(2)) return plan_enqueue(HypNode<T>{}, P, sh, st, used);
     if (p == T(1)) return plan_enqueue(SumNode<T>{}, P, sh, st, used);
     if (__builtin_isinf(p) || p >= cutoff) return plan_enqueue(MaxNode<T>{}, P, sh, st, used);
-    return plan_enqueue(make_lp_node<T>(p), P, sh, st, used);
+    LpNode<T> nd;
+    const int rc = make_lp_node<T>(p, &nd);
+    return rc ? rc : plan_enqueue(nd, P, sh, st, used);
 }
 
 static int plan_enqueue_any(PlanImpl &P, const BatchShape &sh, hipStream_t st, BatchShape *used = nullptr)

@@ -17,7 +17,8 @@
 //   C = Z^a, a = RN(1/p), Z in [1, 2]: with a = a' 2^s, a' <= 2, C = (Z^a')^(2^s).  The top
 //   LP_TAB_BITS fraction bits of Z pick c'_j = RN(2^7 / (2^7 + j)) (the reciprocal of the
 //   interval's left end), R_j = (1/c'_j)^a' and rho_j = R_j - 1 (both rounded from an
-//   extended-precision value, per p, by make_lp_node); with t = fma(Z, c'_j, -1) in
+//   extended-precision value; one device table per (device, p), built and uploaded by
+//   make_lp_node on first use); with t = fma(Z, c'_j, -1) in
 //   [0, 2^-7), Z^a' = R_j (1 + t)^a' and (1 + t)^a' = 1 + u, u = t (b_1 + b_2 t + ... +
 //   b_7 t^6) with the binomial coefficients b_k of a'.  Then Z^a' = 1 + fma(u, R_j, rho_j):
 //   Z = 1 gives exactly 1, and R_j's rounding touches only the small product.
@@ -49,14 +50,6 @@ namespace vnp {
 
 constexpr int LP_TAB_N = 1 << LP_TAB_BITS;
 
-// Per-p tables of the p node (make_lp_node), passed to the kernels by value inside the
-// node and copied to LDS at kernel entry.
-struct LpTables {
-    double b[8];           // binomial coefficients b_1 .. b_7 of a' (b[7] unused)
-    double R[LP_TAB_N];    // R_j = (1/c'_j)^a', rounded
-    double rho[LP_TAB_N];  // rho_j = R_j - 1, rounded from the extended value
-};
-
 // The tables in LDS: one copy per block, filled by lp_table_fill at kernel entry.
 __device__ __forceinline__ double2 *lp_table()
 {
@@ -69,18 +62,19 @@ __device__ __forceinline__ double *lp_ptable()  // c'_j, R_j, rho_j, then b_1 ..
     return tab;
 }
 
-// Every thread of the block calls this before the first node evaluation.
-__device__ __forceinline__ void lp_table_fill(const LpTables &k)
+// Every thread of the block calls this before the first node evaluation.  rr: the per-p
+// device table (R_0 .. R_127, rho_0 .. rho_127); b: the binomial coefficients.
+__device__ __forceinline__ void lp_table_fill(const double *rr, const double *b)
 {
     double2 *tab = lp_table();
     double *pt = lp_ptable();
     for (int i = threadIdx.x; i < LP_TAB_N; i += blockDim.x) {
         tab[i] = make_double2(lp_tab_src[i][0], lp_tab_src[i][1]);
         pt[i] = lp_ptab_src[i];
-        pt[LP_TAB_N + i] = k.R[i];
-        pt[2 * LP_TAB_N + i] = k.rho[i];
+        pt[LP_TAB_N + i] = rr[i];
+        pt[2 * LP_TAB_N + i] = rr[LP_TAB_N + i];
     }
-    if (threadIdx.x < 8) pt[3 * LP_TAB_N + threadIdx.x] = k.b[threadIdx.x];
+    if (threadIdx.x < 8) pt[3 * LP_TAB_N + threadIdx.x] = b[threadIdx.x];
     __syncthreads();
 }
 
@@ -158,8 +152,7 @@ __device__ __forceinline__ double lp_core(double a, double b, double half_p, int
 }
 
 // The evaluation part of the p node: p/2 and s, with every table read from LDS.  Device
-// functions that are not inlined receive this part only (node_eval), so the tables are
-// never copied out of the kernel arguments.
+// functions that are not inlined receive this part only (node_eval).
 template <typename T>
 struct LpEval;
 
@@ -194,18 +187,21 @@ struct LpEval<float> {
     __device__ float finish(float r) const { return r; }
 };
 
-// The p node as the kernels receive it: the evaluation part and the per-p tables.  Its
-// own evaluation (inlined into the kernel body) takes the binomial coefficients from the
-// kernel arguments, which stay in scalar registers.
+// The p node as the kernels receive it: the evaluation part, the binomial coefficients
+// and the device table of R_j and rho_j (small kernel arguments: a large argument block
+// costs several microseconds of host time per launch).  Its own evaluation (inlined into
+// the kernel body) takes the coefficients from the kernel arguments, which stay in
+// scalar registers.
 template <typename T>
 struct LpNode : LpEval<T> {
-    LpTables tab;
-    __device__ T leaf(T a, T b) const
+    double b[8];       // binomial coefficients b_1 .. b_7 of a' (b[7] = 0)
+    const double *rr;  // device: R_0 .. R_127, then rho_0 .. rho_127
+    __device__ T leaf(T a, T b_) const
     {
-        return (T)lp_core((double)__builtin_fabs((double)a), (double)__builtin_fabs((double)b), this->half_p,
-                          this->sq, tab.b);
+        return (T)lp_core((double)__builtin_fabs((double)a), (double)__builtin_fabs((double)b_), this->half_p,
+                          this->sq, b);
     }
-    __device__ T node(T a, T b) const { return (T)lp_core((double)a, (double)b, this->half_p, this->sq, tab.b); }
+    __device__ T node(T a, T b_) const { return (T)lp_core((double)a, (double)b_, this->half_p, this->sq, b); }
     __device__ T finish(T r) const { return r; }
 };
 
@@ -215,65 +211,116 @@ __host__ __device__ inline LpEval<T> node_eval(const LpNode<T> &nd)
     return LpEval<T>{nd.half_p, nd.sq};
 }
 
-template <typename T>
-inline LpNode<T> make_lp_node(T p);
-
 // Kernel-entry hook of the nodes: the p node fills its tables (the other nodes have
 // nothing to set up).
 template <typename T>
 __device__ __forceinline__ void node_prologue(const LpNode<T> &nd)
 {
-    lp_table_fill(nd.tab);
+    lp_table_fill(nd.rr, nd.b);
 }
 
-// The node for half_p = RN(p/2) and a = RN(1/p) (host side; cached, since building the
-// tables takes 2^LP_TAB_BITS extended-precision powers).
-template <typename T>
-inline LpNode<T> lp_node(double half_p, double a)
+// Per-(device, p) constants of the p node, built on first use and kept until
+// release_lp_tables (host side).
+struct LpEntry {
+    int sq;
+    double b[8];
+    double *rr;  // device table
+};
+
+struct LpCache {
+    std::mutex mu;
+    std::map<std::pair<int, std::pair<uint64_t, uint64_t>>, LpEntry> map;
+};
+
+inline LpCache &lp_cache()
 {
-    static std::mutex mu;
-    static std::map<std::pair<uint64_t, uint64_t>, LpNode<T>> cache;
-    uint64_t kh, ka;
-    memcpy(&kh, &half_p, 8);
-    memcpy(&ka, &a, 8);
-    std::lock_guard<std::mutex> lk(mu);
-    auto it = cache.find({kh, ka});
-    if (it != cache.end()) return it->second;
-    LpNode<T> c{};
-    c.half_p = half_p;
-    c.sq = 0;
-    double ap = a;
-    while (ap > 2.0) {  // exact halvings
-        ap = std::ldexp(ap, -1);
-        ++c.sq;
-    }
-    long double bk = 1.0L;
-    for (int i = 1; i <= 7; ++i) {
-        bk = bk * ((long double)ap - (i - 1)) / i;
-        c.tab.b[i - 1] = (double)bk;
-    }
-    c.tab.b[7] = 0.0;
-    for (int j = 0; j < LP_TAB_N; ++j) {
-        const long double r = std::pow(1.0L / (long double)lp_ptab_host[j], (long double)ap);
-        c.tab.R[j] = (double)r;
-        c.tab.rho[j] = (double)(r - 1.0L);
-    }
-    if (cache.size() >= 256) cache.clear();
-    cache.emplace(std::make_pair(kh, ka), c);
+    static LpCache c;
     return c;
 }
 
-template <>
-inline LpNode<double> make_lp_node<double>(double p)
+// The node for half_p = RN(p/2) and a = RN(1/p) on the current device.  The first use of
+// a (device, p) builds the table in extended precision and uploads it (a synchronous
+// copy: outside graph capture); returns 0 or a HIP error code.
+template <typename T>
+inline int lp_node(double half_p, double a, LpNode<T> *out)
 {
-    return lp_node<double>(p * 0.5, 1.0 / p);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    uint64_t kh, ka;
+    memcpy(&kh, &half_p, 8);
+    memcpy(&ka, &a, 8);
+    LpCache &c = lp_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    const auto key = std::make_pair(dev, std::make_pair(kh, ka));
+    auto it = c.map.find(key);
+    if (it == c.map.end()) {
+        LpEntry en{};
+        double ap = a;
+        while (ap > 2.0) {  // exact halvings
+            ap = std::ldexp(ap, -1);
+            ++en.sq;
+        }
+        long double bk = 1.0L;
+        for (int i = 1; i <= 7; ++i) {
+            bk = bk * ((long double)ap - (i - 1)) / i;
+            en.b[i - 1] = (double)bk;
+        }
+        en.b[7] = 0.0;
+        double h[2 * LP_TAB_N];
+        for (int j = 0; j < LP_TAB_N; ++j) {
+            const long double r = std::pow(1.0L / (long double)lp_ptab_host[j], (long double)ap);
+            h[j] = (double)r;
+            h[LP_TAB_N + j] = (double)(r - 1.0L);
+        }
+        e = hipMalloc(reinterpret_cast<void **>(&en.rr), sizeof(h));
+        if (e != hipSuccess) return (int)e;
+        e = hipMemcpy(en.rr, h, sizeof(h), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(en.rr);
+            return (int)e;
+        }
+        it = c.map.emplace(key, en).first;
+    }
+    out->half_p = half_p;
+    out->sq = it->second.sq;
+    memcpy(out->b, it->second.b, sizeof(out->b));
+    out->rr = it->second.rr;
+    return 0;
+}
+
+template <typename T>
+inline int make_lp_node(T p, LpNode<T> *out);
+
+template <>
+inline int make_lp_node<double>(double p, LpNode<double> *out)
+{
+    return lp_node<double>(p * 0.5, 1.0 / p, out);
 }
 
 template <>
-inline LpNode<float> make_lp_node<float>(float p)
+inline int make_lp_node<float>(float p, LpNode<float> *out)
 {
     const float hp = p * 0.5f, ip = 1.0f / p;
-    return lp_node<float>((double)hp, (double)ip);
+    return lp_node<float>((double)hp, (double)ip, out);
+}
+
+// Frees the current device's p-node tables (no work using them may be pending).
+inline int release_lp_tables()
+{
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    LpCache &c = lp_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    for (auto it = c.map.begin(); it != c.map.end();) {
+        if (it->first.first == dev) {
+            (void)hipFree(it->second.rr);
+            it = c.map.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    return 0;
 }
 
 }  // namespace vnp

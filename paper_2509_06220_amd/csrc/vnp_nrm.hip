@@ -281,7 +281,9 @@ static int run_pnorm(int64_t n, const T *x, int64_t incx, T p, T *res, void *str
     if (p == T(2)) return run_norm(HypNode<T>{}, n, x, incx, res, stream);
     if (p == T(1)) return run_norm(SumNode<T>{}, n, x, incx, res, stream);
     if (__builtin_isinf(p) || p >= cutoff) return run_norm(MaxNode<T>{}, n, x, incx, res, stream);
-    return run_norm(make_lp_node<T>(p), n, x, incx, res, stream);
+    LpNode<T> nd;
+    const int rc = make_lp_node<T>(p, &nd);
+    return rc ? rc : run_norm(nd, n, x, incx, res, stream);
 }
 
 }  // namespace vnp
@@ -369,6 +371,7 @@ int vnp_finalize(void)
 {
     release_batch_workspaces();
     release_svd_workspaces();
+    release_lp_tables();
     return release_workspaces();
 }
 
