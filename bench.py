@@ -425,8 +425,9 @@ def main():
                     help="only run one operation K times for a profiler: dnrmf, snrmf (n=2^30) or dnrmp:<p> (n=2^28)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (the multi-GPU sharding "
-              "is a design, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (sharding over several "
+              "GPUs is designed but not built: aligned tile-subtree shards and one all-gather of the roots)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
