@@ -144,3 +144,21 @@ def test_many_distinct_p():
         g = gpu_p(d, p)
         o = float(oracle.nrmp(x, p, "A"))
         assert_parity(g, o, 3000, "f64")
+
+
+@pytest.mark.parametrize("fmt", ["f64", "f32"])
+def test_pnorm_launch_shapes_are_bitwise_identical(fmt):
+    """The p node gives the same bits in every launch shape (small-vector kernel, streaming
+    kernel with a partial tail tile evaluated out of line, several shapes)."""
+    te = 16384 if fmt == "f32" else 8192
+    try:
+        for n in [3 * te + 17, (1 << 20) + 12345]:
+            x = to_dev(vnp_gen.host_fill(n, dtype=fmt, kind="exp", lo=-10, hi=10, seed=8))
+            ref = gpu_p(x, 3.0)
+            for wpb, wt in [(1, 1), (4, 1), (4, 4), (8, 8), (16, 2)]:
+                vnp.set_launch_shape(wpb, wt)
+                assert gpu_p(x, 3.0) == ref, (n, wpb, wt)
+            vnp.set_launch_shape(0, 0)
+            assert gpu_p(x, 3.0) == ref
+    finally:
+        vnp.set_launch_shape(0, 0)
