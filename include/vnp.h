@@ -154,7 +154,8 @@ int vnp_snrmp_mat(int64_t m, int64_t ncols, const float *A, int64_t lda, float p
  * shape chosen by timing candidates on `stream` when autotune is set (the shape never
  * changes a result), longest segments scheduled first when host offsets are given, and
  * the setup + batched launches captured in a HIP graph -- then replayed by
- * vnp_plan_exec.  The plan owns its workspace (so a plan's replays must not overlap
+ * vnp_plan_exec.  The plan owns its workspace and, for a p-norm, its copy of the p
+ * node's table (so it stays valid across vnp_finalize; a plan's replays must not overlap
  * each other); the caller's buffers must stay valid and keep their sizes while the plan
  * exists; their contents may change between replays.
  * Errors (create): plan == NULL -> -1; invalid descriptor -> -2; > 0 HIP error.

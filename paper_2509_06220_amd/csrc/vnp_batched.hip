@@ -737,6 +737,7 @@ struct PlanImpl {
     const void *x = nullptr;
     void *res = nullptr;
     int32_t *order = nullptr;  // device, processing order (longest segments first) or null
+    double *lp_rr = nullptr;   // device, the plan's own copy of its p-node table (p-norm plans)
     BatchShape shape{};
     BatchWorkspace ws;
     hipGraph_t graph = nullptr;
@@ -751,6 +752,33 @@ static int plan_enqueue(const Node &nd, PlanImpl &P, const BatchShape &sh, hipSt
                            P.ws, static_cast<T *>(P.res), st, used);
 }
 
+// The p node of a p-norm plan.  The captured graph keeps the table pointer, so the plan
+// owns a copy of the table (the shared one is released by vnp_finalize); it is made
+// before the capture (plan_prepare).
+template <typename T>
+static int plan_lp_node(PlanImpl &P, T p, LpNode<T> *nd)
+{
+    int rc = make_lp_node<T>(p, nd);
+    if (rc) return rc;
+    if (!P.lp_rr) {
+        const size_t bytes = 2 * LP_TAB_N * sizeof(double);
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&P.lp_rr), bytes);
+        if (e == hipSuccess) e = hipMemcpy(P.lp_rr, nd->rr, bytes, hipMemcpyDeviceToDevice);
+        if (e != hipSuccess) return (int)e;
+    }
+    nd->rr = P.lp_rr;
+    return 0;
+}
+
+template <typename T>
+static int plan_prepare_p(PlanImpl &P, T cutoff)
+{
+    const T p = (T)P.p;
+    if (p == T(2) || p == T(1) || __builtin_isinf(p) || p >= cutoff) return 0;
+    LpNode<T> nd;
+    return plan_lp_node<T>(P, p, &nd);
+}
+
 template <typename T>
 static int plan_enqueue_p(PlanImpl &P, const BatchShape &sh, hipStream_t st, T cutoff, BatchShape *used)
 {
@@ -759,7 +787,7 @@ static int plan_enqueue_p(PlanImpl &P, const BatchShape &sh, hipStream_t st, T c
     if (p == T(1)) return plan_enqueue(SumNode<T>{}, P, sh, st, used);
     if (__builtin_isinf(p) || p >= cutoff) return plan_enqueue(MaxNode<T>{}, P, sh, st, used);
     LpNode<T> nd;
-    const int rc = make_lp_node<T>(p, &nd);
+    const int rc = plan_lp_node<T>(P, p, &nd);
     return rc ? rc : plan_enqueue(nd, P, sh, st, used);
 }
 
@@ -825,6 +853,7 @@ static void plan_free(PlanImpl *P)
     if (P->exec) (void)hipGraphExecDestroy(P->exec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
     if (P->order) (void)hipFree(P->order);
+    if (P->lp_rr) (void)hipFree(P->lp_rr);
     free_batch_ws(P->ws);
     delete P;
 }
@@ -872,6 +901,7 @@ int vnp_plan_create(vnp_plan **plan, const vnp_plan_desc *d, void *stream)
     }
     const int64_t items_cap = d->nseg + (d->n_total + te - 1) / te + 1;
     if (!rc) rc = ensure_batch_ws(P->ws, esz * (size_t)items_cap, (size_t)(d->nseg > 0 ? d->nseg : 1), st);
+    if (!rc) rc = P->dtype == VNP_F32 ? plan_prepare_p<float>(*P, 0x1p24f) : plan_prepare_p<double>(*P, 0x1p53);
     if (!rc && d->autotune && d->nseg > 0) rc = autotune(*P, st);
     if (!rc && d->nseg > 0) {
         // capture on a private stream (the legacy default stream cannot be captured)

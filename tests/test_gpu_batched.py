@@ -159,3 +159,22 @@ def test_batched_argument_errors():
     assert L.vnp_dnrmf_batched(-1, 0, 0, 0, 0, None) == -1
     assert L.vnp_dnrmf_batched(3, 0, 10, 0, 0, None) == -2
     assert L.vnp_dnrmf_cols(5, 2, 1, 4, 1, None) == -4
+
+
+def test_p_plan_outlives_finalize():
+    """A p-norm plan keeps its own copy of the p node's table: after vnp_finalize (which
+    releases the shared tables and workspaces) its replays still equal the plain calls."""
+    off = _segments(9, 120)
+    n = int(off[-1])
+    x = to_dev(vnp_gen.host_fill(n, dtype="f64", kind="u11exp", lo=-20, hi=20, seed=12))
+    doff = to_dev(off)
+    plan = vnp.Plan(x, doff, p=3.0, h_offsets=off, autotune=False)
+    first = plan.run().clone()
+    torch.cuda.synchronize()
+    vnp.finalize()
+    again = plan.run().clone()
+    torch.cuda.synchronize()
+    ref = vnp.nrm_batched(x, doff, p=3.0)
+    torch.cuda.synchronize()
+    assert torch.equal(first, ref) and torch.equal(again, ref)
+    plan.close()
