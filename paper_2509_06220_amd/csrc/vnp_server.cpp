@@ -5,7 +5,7 @@
 // descriptors and item offsets into the slot's pinned host buffer and enqueues the batch:
 // a stage kernel copies the descriptors to the device, then one batched launch per
 // (dtype, p) class writes the results straight into the slot's pinned result buffer, and
-// an event is recorded.  Each slot has a completion thread that waits for that event,
+// an event is recorded.  A batch of one request is the single-vector call itself.  Each slot has a completion thread that waits for that event,
 // posts the results to the tickets and wakes waiters and the batcher.  With several
 // slots, requests that arrive while batches run are launched on another stream and
 // overlap on the device.
@@ -24,6 +24,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "../../include/vnp.h"
 #include "../../include/vnp_server.h"
 #include "vnp_batch.hpp"
 #include "vnp_internal.hpp"
@@ -158,6 +159,24 @@ int vnp_server::launch(Slot &s, std::vector<Pending> &reqs, int *nlaunch)
     *nlaunch = 0;
     const size_t cap = (size_t)cfg.max_batch;
     const int64_t n = (int64_t)reqs.size();
+    if (n == 1) {
+        // one request: the single-vector call itself on the slot's stream (no descriptor
+        // staging), its result written to the slot's pinned result word
+        const vnp_request &q = reqs[0].req;
+        int rc;
+        if (q.dtype == VNP_F32) {
+            float *r = reinterpret_cast<float *>(s.h_res_dev + cap * 8);
+            const float *x = static_cast<const float *>(q.x);
+            rc = q.p == 2.0 ? vnp_snrmf(q.n, x, q.incx, r, s.st) : vnp_snrmp(q.n, x, q.incx, (float)q.p, r, s.st);
+        } else {
+            double *r = reinterpret_cast<double *>(s.h_res_dev);
+            const double *x = static_cast<const double *>(q.x);
+            rc = q.p == 2.0 ? vnp_dnrmf(q.n, x, q.incx, r, s.st) : vnp_dnrmp(q.n, x, q.incx, q.p, r, s.st);
+        }
+        if (rc) return rc;
+        *nlaunch = 1;
+        return (int)hipEventRecord(s.ev, s.st);
+    }
     std::stable_sort(reqs.begin(), reqs.end(), [](const Pending &u, const Pending &v) {
         if (u.req.dtype != v.req.dtype) return u.req.dtype < v.req.dtype;
         return u.req.p < v.req.p;
