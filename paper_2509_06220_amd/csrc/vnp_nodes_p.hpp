@@ -56,9 +56,11 @@ __device__ __forceinline__ double2 *lp_table()
     __shared__ double2 tab[LP_TAB_N];
     return tab;
 }
-__device__ __forceinline__ double *lp_ptable()  // c'_j, R_j, rho_j, then b_1 .. b_7
+// c'_j, R_j, rho_j, then b_1 .. b_7 (and a zero), then the 2^f coefficients of f^11 .. f^1
+constexpr int LP_EXP_OFF = 3 * LP_TAB_N + 8;
+__device__ __forceinline__ double *lp_ptable()
 {
-    __shared__ double tab[3 * LP_TAB_N + 8];
+    __shared__ double tab[LP_EXP_OFF + 11];
     return tab;
 }
 
@@ -75,6 +77,14 @@ __device__ __forceinline__ void lp_table_fill(const double *rr, const double *b)
         pt[2 * LP_TAB_N + i] = rr[LP_TAB_N + i];
     }
     if (threadIdx.x < 8) pt[3 * LP_TAB_N + threadIdx.x] = b[threadIdx.x];
+    if (threadIdx.x < 11) {
+        // 2^f on |f| <= 1/2, degree 11 (Chebyshev fit, relative error 2^-55.5), f^11 first
+        constexpr double E[11] = {0x1.e9ec1fcb69a7fp-32, 0x1.e6228acd1c6e5p-28, 0x1.b524ebd13a55fp-24,
+                                  0x1.62bfc2c86d700p-20, 0x1.ffcbfc6da6ed1p-17, 0x1.430913112c61bp-13,
+                                  0x1.5d87fe78a3f9cp-10, 0x1.3b2ab6fb9f1a5p-7,  0x1.c6b08d704a0c6p-5,
+                                  0x1.ebfbdff82c5aep-3,  0x1.62e42fefa39efp-1};
+        pt[LP_EXP_OFF + threadIdx.x] = E[threadIdx.x];
+    }
     __syncthreads();
 }
 
@@ -94,22 +104,19 @@ __device__ __forceinline__ double log2_part(double f, double &l)
     return t * g;
 }
 
-// 2^y for finite y in [-2100, 2100] (0 and +inf beyond the binary64 range).
+// 2^y for finite y in [-2100, 2100] (0 and +inf beyond the binary64 range).  The
+// coefficients are read from LDS (lp_table_fill): as immediates they exhaust the scalar
+// registers of the streaming kernel, and the compiler then rebuilds each 64-bit
+// coefficient with two vector moves at every use (about a fifth of the node's VALU
+// instructions); from LDS they are loaded once into vector registers.
 __device__ __forceinline__ double exp2_poly(double y)
 {
     const double k = __builtin_rint(y);
     const double f = y - k;  // exact, |f| <= 1/2
-    double t = 0x1.e9ec1fcb69a7fp-32;
-    t = __builtin_fma(t, f, 0x1.e6228acd1c6e5p-28);
-    t = __builtin_fma(t, f, 0x1.b524ebd13a55fp-24);
-    t = __builtin_fma(t, f, 0x1.62bfc2c86d700p-20);
-    t = __builtin_fma(t, f, 0x1.ffcbfc6da6ed1p-17);
-    t = __builtin_fma(t, f, 0x1.430913112c61bp-13);
-    t = __builtin_fma(t, f, 0x1.5d87fe78a3f9cp-10);
-    t = __builtin_fma(t, f, 0x1.3b2ab6fb9f1a5p-7);
-    t = __builtin_fma(t, f, 0x1.c6b08d704a0c6p-5);
-    t = __builtin_fma(t, f, 0x1.ebfbdff82c5aep-3);
-    t = __builtin_fma(t, f, 0x1.62e42fefa39efp-1);
+    const double *E = lp_ptable() + LP_EXP_OFF;  // the same address in every lane
+    double t = E[0];
+#pragma unroll
+    for (int i = 1; i < 11; ++i) t = __builtin_fma(t, f, E[i]);
     t = __builtin_fma(t, f, 1.0);
     return __builtin_amdgcn_ldexp(t, (int)k);
 }
