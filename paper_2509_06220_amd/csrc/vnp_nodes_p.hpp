@@ -56,11 +56,13 @@ __device__ __forceinline__ double2 *lp_table()
     __shared__ double2 tab[LP_TAB_N];
     return tab;
 }
-// c'_j, R_j, rho_j, then b_1 .. b_7 (and a zero), then the 2^f coefficients of f^11 .. f^1
+// c'_j, R_j, rho_j, then b_1 .. b_7 (and a zero), then the 2^f coefficients of f^11 .. f^1,
+// then the log2(1 + t) / t coefficients of t^5 .. t^0
 constexpr int LP_EXP_OFF = 3 * LP_TAB_N + 8;
+constexpr int LP_LOG_OFF = LP_EXP_OFF + 11;
 __device__ __forceinline__ double *lp_ptable()
 {
-    __shared__ double tab[LP_EXP_OFF + 11];
+    __shared__ double tab[LP_LOG_OFF + 6];
     return tab;
 }
 
@@ -85,6 +87,12 @@ __device__ __forceinline__ void lp_table_fill(const double *rr, const double *b)
                                   0x1.ebfbdff82c5aep-3,  0x1.62e42fefa39efp-1};
         pt[LP_EXP_OFF + threadIdx.x] = E[threadIdx.x];
     }
+    if (threadIdx.x < 6) {
+        // log2(1 + t) = t g(t), |t| <= 1.01 * 2^-8, g of degree 5 (absolute error 2^-61.7)
+        constexpr double G[6] = {-0x1.ec72d2e6fb6e9p-3, 0x1.277807fe93552p-2, -0x1.715476524c17ep-2,
+                                 0x1.ec709dc324b6cp-2,  -0x1.71547652b82fep-1, 0x1.71547652b82fep+0};
+        pt[LP_LOG_OFF + threadIdx.x] = G[threadIdx.x];
+    }
     __syncthreads();
 }
 
@@ -95,12 +103,10 @@ __device__ __forceinline__ double log2_part(double f, double &l)
     const double2 e = lp_table()[(hi >> (20 - LP_TAB_BITS)) & (LP_TAB_N - 1)];
     l = e.y;
     const double t = __builtin_fma(f, e.x, -1.0);
-    double g = -0x1.ec72d2e6fb6e9p-3;
-    g = __builtin_fma(g, t, 0x1.277807fe93552p-2);
-    g = __builtin_fma(g, t, -0x1.715476524c17ep-2);
-    g = __builtin_fma(g, t, 0x1.ec709dc324b6cp-2);
-    g = __builtin_fma(g, t, -0x1.71547652b82fep-1);
-    g = __builtin_fma(g, t, 0x1.71547652b82fep+0);
+    const double *G = lp_ptable() + LP_LOG_OFF;  // the same address in every lane (see exp2_poly)
+    double g = G[0];
+#pragma unroll
+    for (int i = 1; i < 6; ++i) g = __builtin_fma(g, t, G[i]);
     return t * g;
 }
 
