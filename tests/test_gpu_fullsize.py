@@ -95,3 +95,35 @@ def test_c2_full_size(p):
 def test_c2_p2_is_frobenius():
     xd, _ = inputs("f64", "c2")
     assert bits(vnp.nrmp(xd, 2.0).item(), "f64") == bits(vnp.nrmf(xd).item(), "f64")
+
+
+def test_c3_full_size():
+    """The batched workload at its benchmark size (8192 FP64 segments, lengths
+    floor(2^(20U)), about 6.4e8 elements generated on the device): the autotuned,
+    graph-captured plan equals the direct batched call bitwise on every segment, and
+    sampled segments (the longest, the shortest, random ones) meet the parity bar
+    against the oracle."""
+    lens = vnp_gen.log_uniform_lengths(8192, 0, 20, seed=0, stream=7)
+    off = np.zeros(8193, dtype=np.int64)
+    off[1:] = np.cumsum(lens)
+    total = int(off[-1])
+    r = vnp_gen.recipe("c3_values")
+    x = torch.empty(total, dtype=torch.float64, device="cuda")
+    vnp_gen.dev_fill(x, kind=r["kind"], lo=r["lo"], hi=r["hi"], seed=r["seed"], stream=r["stream"])
+    doff = torch.from_numpy(off).cuda()
+    plan = vnp.Plan(x, doff, h_offsets=off, autotune=True)
+    got = plan.run().clone()
+    direct = vnp.nrm_batched(x, doff)
+    torch.cuda.synchronize()
+    print(f"c3: {total} elements, plan {plan.info()}", flush=True)
+    g = got.cpu().numpy()
+    assert np.array_equal(g.view(np.uint64), direct.cpu().numpy().view(np.uint64))
+    order = np.argsort(lens, kind="stable")
+    rng = np.random.default_rng(3)
+    sample = sorted(set(order[-4:].tolist()) | set(order[:4].tolist()) | set(rng.choice(8192, 24, replace=False).tolist()))
+    for s in sample:
+        seg = x[int(off[s]):int(off[s + 1])].cpu().numpy()
+        o = float(oracle.nrmf(seg))
+        assert_parity(float(g[s]), o, seg.size, "f64", f"segment {s}, length {seg.size}")
+    plan.close()
+    del x
