@@ -127,3 +127,45 @@ def test_c3_full_size():
         assert_parity(float(g[s]), o, seg.size, "f64", f"segment {s}, length {seg.size}")
     plan.close()
     del x
+
+
+def test_indices_beyond_32_bits():
+    """Element indices past 2^32 and byte offsets past 2^34.  The canonical tree's root
+    over T tiles (2^k < T <= 2^(k+1)) is the node of the first 2^k tiles' root and the
+    rest's root (zero padding is exact), so for binary32 and n = 2^32 + r:
+    nrmf(x) = node(nrmf(x[:2^32]), nrmf(x[2^32:])) bitwise, with the node taken from a
+    two-element call; one level down the same holds for x[:2^32].  Then binary64 with
+    incx = +-2 over a 16 GiB buffer equals the contiguous (reversed) copy bitwise."""
+    te = vnp.tile_elems(vnp.F32)
+    assert te == 1 << 14
+    big = 1 << 32
+    n = big + 3 * te + 37
+    print(f"binary32 n = {n}", flush=True)
+    x = torch.empty(n, dtype=torch.float32, device="cuda")
+    vnp_gen.dev_fill(x, kind="u11", seed=11, stream=3)
+
+    def node(a, b):
+        pair = torch.stack([a, b]).contiguous()
+        return vnp.nrm_batched(pair, torch.tensor([0, 2], dtype=torch.int64, device="cuda"))[0]
+
+    whole = vnp.nrmf(x)
+    left = vnp.nrmf(x[:big])
+    right = vnp.nrmf(x[big:])
+    assert bits(whole.item(), "f32") == bits(node(left, right).item(), "f32")
+    half = big >> 1
+    assert bits(left.item(), "f32") == bits(node(vnp.nrmf(x[:half]), vnp.nrmf(x[half:big])).item(), "f32")
+    # a plain magnitude check: U[0, 1) elements give about sqrt(n / 3)
+    assert abs(whole.item() / math.sqrt(n / 3.0) - 1.0) < 1e-3
+    del x, whole, left, right
+    torch.cuda.empty_cache()
+
+    m = (1 << 30) + 5
+    print(f"binary64 n = {m}, incx = +-2", flush=True)
+    xd = torch.empty(2 * m, dtype=torch.float64, device="cuda")
+    vnp_gen.dev_fill(xd, kind="u11", seed=12, stream=3)
+    xs = xd[0:2 * m - 1:2].contiguous()
+    fwd = vnp.nrmf(xd, n=m, incx=2).item()
+    assert bits(fwd, "f64") == bits(vnp.nrmf(xs).item(), "f64")
+    rev = vnp.nrmf(xd, n=m, incx=-2).item()
+    assert bits(rev, "f64") == bits(vnp.nrmf(xs.flip(0).contiguous()).item(), "f64")
+    del xd, xs
