@@ -226,8 +226,21 @@ constexpr int COARSE_MAX = 4096;  // LDS entries of the item-offset index (32 Ki
 
 // GEN: segments may be strided or not element-aligned (the generic loader is compiled
 // in); without it every segment takes the vector-load path, which needs fewer registers.
+// Waves per SIMD the streaming kernel's registers must allow: 4 for the binary64 p node
+// (at most 128 VGPRs, which its contiguous variants fit without spilling; uncapped it takes
+// 184 and runs 2 waves per SIMD), 1 (no cap beyond the block size) otherwise.  The
+// binary32 p node would spill hundreds of registers under the same cap.
+template <class Node>
+struct BatchedWavesPerEU {
+    static constexpr int value = 1;
+};
+template <>
+struct BatchedWavesPerEU<LpNode<double>> {
+    static constexpr int value = 4;
+};
+
 template <class Node, class Seg, int U, bool GEN>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(BatchedWavesPerEU<Node>::value)))
     batched_kernel(Node nd, Seg seg, const typename Node::T *x, int64_t nseg, const int32_t *order,
                    const int64_t *item_off, int lwt, typename Node::T *roots, typename Node::T *res)
 {
