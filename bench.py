@@ -121,8 +121,9 @@ def cpu_baseline(n_sample: int):
 
 def oracle_timings(x_c1):
     """The oracle's recursions A and H timed on the host, single-threaded and on all the
-    threads it uses: C0 (n = 2^20, U[-1,1), seed 0) and, all threads only, the C1 vector
-    (x_c1, 2^30 elements); with the CPU model and core count (informational)."""
+    threads it uses: C0 (n = 2^20, U[-1,1), seed 0) with both, and the C1 vector (x_c1,
+    2^30 elements) with H (A on all threads is the CPU baseline); with the CPU model and
+    core count (informational)."""
     import os
 
     import oracle
@@ -152,6 +153,7 @@ def oracle_timings(x_c1):
     for method in ("A", "H"):
         run(f"C0 O-{method} 1 thread", x0, method, 1)
         run(f"C0 O-{method} {threads} threads", x0, method, threads)
+    run(f"C1 O-H 1 thread", x_c1, "H", 1)
     run(f"C1 O-H {threads} threads", x_c1, "H", threads)
     return out
 
