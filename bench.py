@@ -239,7 +239,7 @@ def extra_modes(torch, vnp, vnp_gen):
     return out
 
 
-def batched_mode(torch, vnp, vnp_gen, reps=10):
+def batched_mode(torch, vnp, vnp_gen, reps=20):
     """8192 FP64 segments, lengths floor(2^(20U)), values U[-1,1) 2^e, e in [-30, 30] per
     element: one replay of the autotuned, graph-captured plan against 8192 plain calls
     issued back to back from native code on the same stream; every segment bitwise equal."""
@@ -272,6 +272,9 @@ def batched_mode(torch, vnp, vnp_gen, reps=10):
             "elements": total, "bytes": total * 8,
             "batched_norms_per_s": round(nseg / tb, 1), "batched_ms": round(tb * 1e3, 4),
             "batched_kernel_ms_mean": round(statistics.mean(per_b), 4),
+            "batched_kernel_ms_median": round(statistics.median(per_b), 4),
+            "batched_kernel_ms_min": round(min(per_b), 4), "batched_kernel_ms_max": round(max(per_b), 4),
+            "batched_replays_timed": reps,
             "batched_gbs": round(total * 8 / tb / 1e9, 1),
             "plain_loop_norms_per_s": round(nseg / tl, 1), "plain_loop_ms": round(tl * 1e3, 4),
             "speedup": round(tl / tb, 2), "bitwise_equal_segments": same, "segments": nseg, "plan": info}
