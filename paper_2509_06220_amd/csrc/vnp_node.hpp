@@ -93,23 +93,30 @@ __device__ __forceinline__ double hyp_d(double a, double b)
 __device__ __forceinline__ double hyp_d_leaf(double a, double b) { return hyp_d(a, b); }
 
 // sqrt(s) to about 2^-44 relative (one Goldschmidt step from v_rsq_f64), for s in
-// [2^-767, 2^1023]; +0, +inf and NaN map to themselves.  Rounded to binary32 this is the
-// correctly rounded single-precision root except within 2^-19 ulp of a rounding
-// boundary.
+// [2^-767, 2^1023]; NaN for s = +0 and s = +inf (0 * inf), NaN for NaN.  Rounded to
+// binary32 this is the correctly rounded single-precision root except within 2^-19 ulp of
+// a rounding boundary.
 __device__ __forceinline__ double sqrt_for_f32(double s)
 {
     const double y = __builtin_amdgcn_rsq(s);
     const double g = s * y;
     const double h = y * 0.5;
     const double r = __builtin_fma(-h, g, 0.5);
-    const double g1 = __builtin_fma(g, r, g);
-    return __builtin_amdgcn_class(s, 0x260) ? s : g1;
+    return __builtin_fma(g, r, g);
 }
 
+// The special cases come from a bound instead of a class test.  s = a^2 + b^2 of binary32
+// values is +0 only for a = b = 0, +inf only for an infinite input, and otherwise lies in
+// [2^-298, 2^257]; there the rounded root is at most RN32(|a| + |b|) (the hypotenuse is
+// below |a| + |b|, and where the root's 2^-44 error could cross that sum, the smaller
+// operand is below 2^-42 of the larger and both round to the larger), so the minimum
+// picks it.  For +0 and +inf the root is NaN and the minimum picks |a| + |b|: +0 or
+// +inf.  A NaN input makes both operands NaN.
 __device__ __forceinline__ float hyp_s(float a, float b)
 {
     const double A = (double)a, B = (double)b;
-    return (float)sqrt_for_f32(__builtin_fma(A, A, B * B));
+    const float g = (float)sqrt_for_f32(__builtin_fma(A, A, B * B));
+    return __builtin_fminf(g, __builtin_fabsf(a) + __builtin_fabsf(b));
 }
 
 __device__ __forceinline__ float hyp_s_leaf(float a, float b) { return hyp_s(a, b); }
