@@ -81,6 +81,37 @@ def test_node_via_two_element_segments(fmt):
     assert np.array_equal(z, a.astype(dt))  # node(a, 0) = |a| exactly
 
 
+def test_binary32_node_special_values_and_tiny_ratios():
+    """The binary32 hypot node takes its special values from min(root, |a| + |b|): signed
+    zeros give +0, an infinity gives +inf, a NaN gives NaN (also next to an infinity), and
+    a smaller operand below 2^-13 of the larger leaves exactly the larger one (the
+    correctly rounded result there), down to ratios of 2^-70 and into the subnormals."""
+    rng = np.random.default_rng(23)
+    k = 4096
+    a = ((rng.random(k) + 0.5) * np.exp2(rng.integers(-100, 120, k).astype(np.float64))).astype(np.float32)
+    b = (a.astype(np.float64) * np.exp2(-rng.integers(13, 71, k).astype(np.float64))
+         * (rng.random(k) + 0.5)).astype(np.float32)
+    sa, sb = rng.random(k) < 0.5, rng.random(k) < 0.5
+    a[sa], b[sb] = -a[sa], -b[sb]
+    sp = np.array([[-0.0, -0.0], [0.0, -0.0], [-0.0, 3.5], [-2.5, 0.0], [-np.inf, 1.0], [1.0, np.inf],
+                   [-np.inf, -np.inf], [np.nan, 1.0], [2.0, np.nan], [-np.inf, np.nan], [np.nan, np.inf],
+                   [1e-45, -1e-45], [3e38, 3e38], [-3e38, 1e-45]], dtype=np.float32)
+    x = np.concatenate([np.stack([a, b], 1), sp]).reshape(-1)
+    off = np.arange(0, x.size + 1, 2, dtype=np.int64)
+    r = vnp.nrm_batched(to_dev(x), to_dev(off)).cpu().numpy()
+    big = np.maximum(np.abs(a), np.abs(b))
+    assert np.array_equal(r[:k].view(np.uint32), big.view(np.uint32))
+    got = r[k:]
+    assert got[0] == 0.0 and not np.signbit(got[0]) and got[1] == 0.0 and not np.signbit(got[1])
+    assert got[2] == 3.5 and got[3] == 2.5
+    assert np.all(np.isposinf(got[4:7]))
+    assert np.all(np.isnan(got[7:11]))
+    for i, (u, v) in enumerate(sp[11:]):
+        c = oracle.cr_hypotf(float(u), float(v))
+        g = float(got[11 + i])
+        assert (g == c) if math.isinf(c) else abs(g - c) <= 2.0 ** -24 * c * 1.0001, (u, v, g, c)
+
+
 @pytest.mark.parametrize("fmt", ["f64", "f32"])
 @pytest.mark.parametrize("p", [2.0, 3.0, 0.5])
 def test_node_symmetric_and_monotone(fmt, p):
