@@ -11,6 +11,10 @@
  * Each result is bitwise equal to the single-vector call on the same data (same
  * canonical tree), alone or in any mix.
  *
+ * Threads: the batcher and one completion thread per stream.  While idle, each polls for
+ * new work for up to 200 microseconds before it blocks, so an active server keeps up to
+ * streams + 1 host cores busy for that long after its last request.
+ *
  * Conventions as in vnp.h: 0 = success, -k = argument k invalid, > 0 = HIP error or one
  * of VNP_EAGAIN / VNP_ENOTFOUND / VNP_EPENDING.  All functions are thread-safe.
  */

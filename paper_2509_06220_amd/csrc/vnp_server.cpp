@@ -9,15 +9,21 @@
 // posts the results to the tickets and wakes waiters and the batcher.  With several
 // slots, requests that arrive while batches run are launched on another stream and
 // overlap on the device.
+//
+// The batcher and the completion threads poll for new work for up to SPIN_NS before they
+// block on a condition variable: waking a blocked thread takes longer than a small batch
+// runs on the device.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -35,6 +41,19 @@ int64_t now_ns()
 {
     return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
         .count();
+}
+
+constexpr int64_t SPIN_NS = 200000;  // busy-poll window before blocking
+
+// Polls seq until it differs from seen (true) or spin_ns pass (false).
+bool spin_until_changed(const std::atomic<uint64_t> &seq, uint64_t seen, int64_t spin_ns)
+{
+    const int64_t t0 = now_ns();
+    while (seq.load(std::memory_order_acquire) == seen) {
+        if (now_ns() - t0 > spin_ns) return false;
+        std::this_thread::yield();
+    }
+    return true;
 }
 
 // First-fit allocator over one device allocation, 256-byte granules, with coalescing.
@@ -142,6 +161,11 @@ struct vnp_server {
     std::vector<Slot> slots;
     std::thread worker;
     bool stop = false;
+    // Bumped under mu whenever the batcher may have work (a request queued, a slot freed,
+    // stop), and per slot whenever the slot's batch is in flight (or stop): the polled
+    // change counters of the busy-poll phase.
+    std::atomic<uint64_t> work_seq{0};
+    std::unique_ptr<std::atomic<uint64_t>[]> flight_seq;
     uint64_t next_ticket = 1;
     vnp_server_stats st{};
     int64_t batch_counter = 0;
@@ -245,6 +269,7 @@ void vnp_server::complete(Slot &s, int status)
     }
     s.reqs.clear();
     s.state = SlotState::Free;
+    work_seq.fetch_add(1, std::memory_order_release);
     cv_done.notify_all();
     cv_work.notify_one();
 }
@@ -254,9 +279,17 @@ void vnp_server::completion_loop(size_t i)
 {
     (void)hipSetDevice(device);
     Slot &s = slots[i];
+    std::atomic<uint64_t> &seq = flight_seq[i];
+    auto ready = [&] { return s.state == SlotState::InFlight || (stop && s.state == SlotState::Free); };
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
-        cv_slots.wait(lk, [&] { return s.state == SlotState::InFlight || (stop && s.state == SlotState::Free); });
+        while (!ready()) {
+            const uint64_t seen = seq.load(std::memory_order_relaxed);
+            lk.unlock();
+            const bool changed = spin_until_changed(seq, seen, SPIN_NS);
+            lk.lock();
+            if (!changed) cv_slots.wait(lk, [&] { return ready() || seq.load(std::memory_order_relaxed) != seen; });
+        }
         if (s.state != SlotState::InFlight) break;
         int rc = s.launch_rc;
         lk.unlock();
@@ -294,10 +327,16 @@ void vnp_server::worker_loop()
             if (!go) wait_ns = (int64_t)cfg.max_wait_us * 1000 - age;
         }
         if (!go) {
-            if (wait_ns > 0)
+            if (wait_ns > 0) {
                 cv_work.wait_for(lk, std::chrono::nanoseconds(wait_ns));
-            else
-                cv_work.wait(lk);
+            } else {
+                const uint64_t seen = work_seq.load(std::memory_order_relaxed);
+                lk.unlock();
+                const bool changed = spin_until_changed(work_seq, seen, SPIN_NS);
+                lk.lock();
+                if (!changed)
+                    cv_work.wait(lk, [&] { return work_seq.load(std::memory_order_relaxed) != seen; });
+            }
             continue;
         }
         std::vector<Pending> batch;
@@ -337,6 +376,7 @@ void vnp_server::worker_loop()
         s.launch_rc = rc;
         s.t_enqueued = t_e;
         s.state = SlotState::InFlight;
+        flight_seq[(size_t)(&s - slots.data())].fetch_add(1, std::memory_order_release);
         cv_slots.notify_all();
     }
 }
@@ -378,6 +418,12 @@ int vnp_server_create(vnp_server **srv, const vnp_server_config *cfg)
     const size_t cap = (size_t)cfg->max_batch;
     const size_t desc_bytes = (4 * cap + 32) * 8;  // ptrs | lens | incs | item offsets (+1 per class)
     s->slots.resize((size_t)cfg->streams);
+    s->flight_seq.reset(new (std::nothrow) std::atomic<uint64_t>[(size_t)cfg->streams]);
+    if (!s->flight_seq) {
+        delete s;
+        return (int)hipErrorOutOfMemory;
+    }
+    for (int k = 0; k < cfg->streams; ++k) s->flight_seq[k].store(0, std::memory_order_relaxed);
     for (Slot &sl : s->slots) {
         if (e != hipSuccess) break;
         e = hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking);
@@ -408,11 +454,13 @@ int vnp_server_destroy(vnp_server *s)
         std::lock_guard<std::mutex> lk(s->mu);
         s->stop = true;
         s->pending.clear();
+        s->work_seq.fetch_add(1, std::memory_order_release);
     }
     s->cv_work.notify_all();
     if (s->worker.joinable()) s->worker.join();
     {
         std::lock_guard<std::mutex> lk(s->mu);  // the batcher has stopped: no slot is Launching
+        for (size_t k = 0; k < s->slots.size(); ++k) s->flight_seq[k].fetch_add(1, std::memory_order_release);
     }
     s->cv_slots.notify_all();
     for (Slot &sl : s->slots)
@@ -472,6 +520,7 @@ int vnp_server_submit(vnp_server *s, const vnp_request *req, uint64_t *ticket)
             s->st.rejected += 1;
         } else {
             s->pending.push_back(Pending{id, *req, t, false});
+            s->work_seq.fetch_add(1, std::memory_order_release);
         }
         s->tickets.emplace(id, tk);
         *ticket = id;
