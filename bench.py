@@ -427,7 +427,8 @@ def main():
     ap.add_argument("--study-n-log2", type=int, default=26)
     ap.add_argument("--study-seeds", type=int, default=31)
     ap.add_argument("--profile-op", default=None,
-                    help="only run one operation K times for a profiler: dnrmf, snrmf (n=2^30) or dnrmp:<p> (n=2^28)")
+                    help="only run one operation K times for a profiler: dnrmf, snrmf (n=2^30), dnrmp:<p> "
+                         "(n=2^28) or batched:<p> (the 8192 FP64 segments, direct batched call)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (sharding over several "
@@ -468,6 +469,22 @@ def main():
             xo = torch.empty(n, dtype=torch.float64, device="cuda")
             vnp_gen.dev_fill(xo, kind="exp", lo=-10, hi=10, seed=0)
             fn = lambda: vnp.nrmp(xo, pv)  # noqa: E731
+        elif op.startswith("batched:"):
+            # the C3 segments (8192 FP64 lengths floor(2^(20U)), values as in C3) through the
+            # direct batched call at exponent p
+            import numpy as np
+
+            pv = float(op.split(":", 1)[1])
+            lens = vnp_gen.log_uniform_lengths(8192, 0, 20, seed=0, stream=7)
+            off = np.zeros(8193, dtype=np.int64)
+            off[1:] = np.cumsum(lens)
+            n = int(off[-1])
+            rv = vnp_gen.recipe("c3_values")
+            xo = torch.empty(n, dtype=torch.float64, device="cuda")
+            vnp_gen.dev_fill(xo, kind=rv["kind"], lo=rv["lo"], hi=rv["hi"], seed=rv["seed"], stream=rv["stream"])
+            d_off = torch.from_numpy(off).to("cuda")
+            res_b = torch.empty(8192, dtype=torch.float64, device="cuda")
+            fn = lambda: vnp.nrm_batched(xo, d_off, p=pv, out=res_b)  # noqa: E731
         else:
             print(f"unknown --profile-op {op}", file=sys.stderr)
             sys.exit(2)
