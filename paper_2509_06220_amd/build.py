@@ -31,15 +31,18 @@ def hipcc() -> str:
 
 def build(verbose: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    objs = []
-    for s in srcs:
+    objs, procs = [], []
+    for s in srcs:  # the translation units compile in parallel
         o = os.path.join(CSRC, os.path.basename(s) + ".o")
         lang = [] if s.endswith(".hip") else ["-x", "hip"]
         cmd = [hipcc(), *HIP_FLAGS, *lang, "-c", s, "-o", o]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        procs.append((cmd, subprocess.Popen(cmd)))
         objs.append(o)
+    failed = [cmd for cmd, pr in procs if pr.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp, "-L/opt/rocm/lib", "-lrocsolver",
            "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
