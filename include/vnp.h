@@ -25,6 +25,9 @@
  *     surface at the next synchronization, not here.  Nothing aborts or throws across
  *     the ABI.
  *   - n <= 0 (or nseg segments of length 0) give a result of +0.
+ *   - "p invalid" below: p <= 0, p NaN, or p so small that 1/p rounded once in the
+ *     working precision overflows (p below about 2^-1024 for D, 2^-128 for S; the node of
+ *     Sect. 4 is built from RN(1/p)).  A binary32 call rounds p to binary32 first.
  *   - Special values: any NaN element gives NaN; otherwise any infinite element gives
  *     +inf; otherwise the tree result, which is +inf only if the norm overflows.
  *   - Calls on different streams may run concurrently; each (device, stream) pair gets
@@ -58,6 +61,7 @@ extern "C" {
 #define VNP_EAGAIN 100000 /* resource temporarily exhausted (server pool full) */
 #define VNP_ENOTFOUND 100001 /* unknown ticket */
 #define VNP_EPENDING 100002 /* ticket not complete yet */
+#define VNP_ECANCELED 100003 /* request dropped unlaunched by vnp_server_destroy */
 
 /* ------------------------------------------------------------------------------------
  * Single vector.  Paper: xNRMF (Sect. 1; the recommended algorithm of Sect. 3) and
@@ -66,7 +70,7 @@ extern "C" {
  * x[(n - 1 - i) * (-incx)] for incx <= -1.  incx == 0 is invalid (-3).
  * The result is written to *res (one element of the working precision).
  * Errors: n > VNP_MAX_N -> -1; x == NULL with n > 0 -> -2; incx == 0 -> -3;
- * p <= 0 or NaN -> -4 (nrmp only); res == NULL -> -4 (nrmf) / -5 (nrmp).
+ * p invalid -> -4 (nrmp only); res == NULL -> -4 (nrmf) / -5 (nrmp).
  * ---------------------------------------------------------------------------------- */
 #define VNP_MAX_N (((int64_t)1) << 40)
 
@@ -90,7 +94,7 @@ int vnp_snrmp(int64_t n, const float *x, int64_t incx, float p, float *res, void
  * on first use and may synchronize its stream when the workspace grows.
  * m, n, lda <= 2^31 - 1.
  * Errors: m invalid -> -1; n invalid -> -2; A == NULL -> -3; lda < max(1, m) -> -4;
- * p <= 0 or NaN -> -5; res == NULL -> -6. */
+ * p invalid -> -5; res == NULL -> -6. */
 int vnp_dschatten(int64_t m, int64_t n, const double *A, int64_t lda, double p, double *res, void *stream);
 int vnp_sschatten(int64_t m, int64_t n, const float *A, int64_t lda, float p, float *res, void *stream);
 
@@ -113,7 +117,7 @@ int vnp_scnrmf(int64_t n, const float *z, int64_t incz, float *res, void *stream
  * persistent launch, preceded by a one-block setup launch and followed by a finish
  * launch that reduces the run roots of long segments, with a per-stream workspace.
  * Errors: nseg < 0 -> -1; offsets == NULL -> -2; n_total < 0 or > VNP_MAX_N -> -3;
- * x == NULL -> -4; res == NULL -> -5 (p-norm: p <= 0 or NaN -> -5, res == NULL -> -6).
+ * x == NULL -> -4; res == NULL -> -5 (p-norm: p invalid -> -5, res == NULL -> -6).
  * A segment reaching outside [0, n_total) is detected on the device: then every res[s]
  * is NaN and no data is read.
  * ---------------------------------------------------------------------------------- */
@@ -142,7 +146,7 @@ int vnp_snrmf_cols(int64_t m, int64_t ncols, const float *A, int64_t lda, float 
  * binary tree over the column index (zero-padded, with the same node), one value written
  * to *res.  Rows m .. lda-1 are never read.  Device pointers; stream-ordered.
  * Errors: m < 0 -> -1; ncols < 0 -> -2; A == NULL (with m, ncols > 0) -> -3;
- * lda < max(1, m) or the array spans more than VNP_MAX_N elements -> -4; p <= 0 or NaN
+ * lda < max(1, m) or the array spans more than VNP_MAX_N elements -> -4; p invalid
  * -> -5 (p variants); res == NULL -> -5 (-6 for the p variants). */
 int vnp_dnrmf_mat(int64_t m, int64_t ncols, const double *A, int64_t lda, double *res, void *stream);
 int vnp_snrmf_mat(int64_t m, int64_t ncols, const float *A, int64_t lda, float *res, void *stream);

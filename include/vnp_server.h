@@ -63,11 +63,15 @@ typedef struct {
     int64_t host_launch_ns;  /* total host time spent enqueueing batches */
     int64_t batch_ns;        /* total time from a batch's enqueue to its completion being seen */
     int64_t batch_ns_max;    /* longest such time */
+    int64_t cancelled;       /* requests completed as VNP_ECANCELED by vnp_server_destroy */
 } vnp_server_stats;
 
 /* Errors: srv == NULL -> -1; cfg invalid -> -2; > 0 HIP error (pool allocation). */
 int vnp_server_create(vnp_server **srv, const vnp_server_config *cfg);
-/* Finishes the batches in flight, drops pending requests, frees the pool. */
+/* Finishes the batches in flight; requests not yet launched complete with status
+ * VNP_ECANCELED (value NaN).  Threads blocked in vnp_server_wait return their ticket's
+ * result before the server is freed; no call may start on srv once destroy has begun.
+ * Then frees the pool and the server. */
 int vnp_server_destroy(vnp_server *srv);
 
 /* Device memory from the pool (256-byte aligned).  VNP_EAGAIN if no free block is large
@@ -78,9 +82,9 @@ int vnp_server_free(vnp_server *srv, void *dptr);
 
 /* Queues a request; *ticket identifies it.  An invalid request is accepted and completes
  * at once with its INFO code in vnp_result.status (n < 0 or > VNP_MAX_N -> -3, x NULL ->
- * -4, incx == 0 -> -5, p <= 0 or NaN -> -2, unknown dtype -> -1).  The payload must stay
- * valid until the request completes.  Errors of the call: srv NULL -> -1; req NULL -> -2;
- * ticket NULL -> -3. */
+ * -4, incx == 0 -> -5, p invalid for the request's dtype (as in vnp.h) -> -2, unknown
+ * dtype -> -1).  The payload must stay valid until the request completes.  Errors of the
+ * call: srv NULL -> -1; req NULL -> -2; ticket NULL -> -3. */
 int vnp_server_submit(vnp_server *srv, const vnp_request *req, uint64_t *ticket);
 /* Non-blocking: 0 and *out filled (and the ticket released) if done, else VNP_EPENDING;
  * VNP_ENOTFOUND for an unknown or already released ticket. */

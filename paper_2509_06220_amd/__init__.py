@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libvnp.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "vnp.h")
 
 F64, F32 = 0, 1
-EAGAIN, ENOTFOUND, EPENDING = 100000, 100001, 100002
+EAGAIN, ENOTFOUND, EPENDING, ECANCELED = 100000, 100001, 100002, 100003
 
 
 class VnpError(RuntimeError):
@@ -319,7 +319,7 @@ class ServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "rejected", "batches", "launches",
                                               "failed_batches", "max_batch_seen", "pool_free_bytes", "pool_bytes",
                                               "pending", "in_flight", "host_launch_ns", "batch_ns",
-                                              "batch_ns_max")]
+                                              "batch_ns_max", "cancelled")]
 
 
 class Server:

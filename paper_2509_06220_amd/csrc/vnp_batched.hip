@@ -885,7 +885,8 @@ int vnp_plan_create(vnp_plan **plan, const vnp_plan_desc *d, void *stream)
 {
     if (!plan) return -1;
     *plan = nullptr;
-    if (!d || (d->dtype != VNP_F64 && d->dtype != VNP_F32) || !(d->p > 0) || d->nseg < 0 || d->n_total < 0 ||
+    if (!d || (d->dtype != VNP_F64 && d->dtype != VNP_F32) ||
+        !(d->dtype == VNP_F32 ? p_ok((float)d->p) : p_ok(d->p)) || d->nseg < 0 || d->n_total < 0 ||
         (d->nseg > 0 && (!d->offsets || !d->res)) || (d->n_total > 0 && !d->x))
         return -2;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -996,7 +997,7 @@ int vnp_dnrmp_batched(int64_t nseg, const int64_t *offsets, int64_t n_total, con
     if (nseg > 0 && !offsets) return -2;
     if (n_total < 0 || n_total > VNP_MAX_N) return -3;
     if (nseg > 0 && n_total > 0 && !x) return -4;
-    if (!(p > 0)) return -5;
+    if (!p_ok(p)) return -5;
     if (nseg > 0 && !res) return -6;
     return run_batched_p<double>(SegOffsets{offsets}, x, nseg, n_total, p, res, stream, 0x1p53);
 }
@@ -1008,7 +1009,7 @@ int vnp_snrmp_batched(int64_t nseg, const int64_t *offsets, int64_t n_total, con
     if (nseg > 0 && !offsets) return -2;
     if (n_total < 0 || n_total > VNP_MAX_N) return -3;
     if (nseg > 0 && n_total > 0 && !x) return -4;
-    if (!(p > 0)) return -5;
+    if (!p_ok(p)) return -5;
     if (nseg > 0 && !res) return -6;
     return run_batched_p<float>(SegOffsets{offsets}, x, nseg, n_total, p, res, stream, 0x1p24f);
 }
@@ -1070,7 +1071,7 @@ int vnp_dnrmp_mat(int64_t m, int64_t ncols, const double *A, int64_t lda, double
 {
     const int a = mat_args(m, ncols, A, lda);
     if (a) return a;
-    if (!(p > 0)) return -5;
+    if (!p_ok(p)) return -5;
     if (!res) return -6;
     if (m == 0 || ncols == 0) return vnp_dnrmp(0, A, 1, p, res, stream);
     if (lda == m || ncols == 1) return vnp_dnrmp(m * ncols, A, 1, p, res, stream);
@@ -1081,7 +1082,7 @@ int vnp_snrmp_mat(int64_t m, int64_t ncols, const float *A, int64_t lda, float p
 {
     const int a = mat_args(m, ncols, A, lda);
     if (a) return a;
-    if (!(p > 0)) return -5;
+    if (!p_ok(p)) return -5;
     if (!res) return -6;
     if (m == 0 || ncols == 0) return vnp_snrmp(0, A, 1, p, res, stream);
     if (lda == m || ncols == 1) return vnp_snrmp(m * ncols, A, 1, p, res, stream);

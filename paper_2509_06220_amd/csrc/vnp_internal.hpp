@@ -84,6 +84,15 @@ struct MaxNode<float> {
     __device__ float finish(float r) const { return r; }
 };
 
+// The p values the p-norm calls accept: p > 0 (not NaN) whose reciprocal, rounded once in
+// the working precision, is finite (the node is built from RN(1/p), Sect. 4); a p below
+// that (about 2^-1024 in binary64, 2^-128 in binary32) is an invalid argument.
+template <typename T>
+__host__ __device__ inline bool p_ok(T p)
+{
+    return p > T(0) && __builtin_isfinite(T(1) / p);
+}
+
 // Rows per load group (one group is in flight per wave while the previous one is
 // reduced): 8 KiB per wave for the binary64 hypot node, 4 KiB where the node is heavier
 // in registers or arithmetic (measured on MI355X; results never depend on it).

@@ -268,6 +268,9 @@ inline int lp_node(double half_p, double a, LpNode<T> *out)
     const auto key = std::make_pair(dev, std::make_pair(kh, ka));
     auto it = c.map.find(key);
     if (it == c.map.end()) {
+        // a = RN(1/p) must be finite (the entry points reject a smaller p); the halvings
+        // below then end after at most 1024 steps
+        if (!(a >= 0.0 && a <= 0x1.fffffffffffffp1023)) return (int)hipErrorInvalidValue;
         LpEntry en{};
         double ap = a;
         while (ap > 2.0) {  // exact halvings

@@ -333,7 +333,7 @@ int vnp_dnrmp(int64_t n, const double *x, int64_t incx, double p, double *res, v
     if (n > VNP_MAX_N) return -1;
     if (n > 0 && !x) return -2;
     if (incx == 0) return -3;
-    if (!(p > 0)) return -4;
+    if (!p_ok(p)) return -4;
     if (!res) return -5;
     return run_pnorm<double>(n, x, incx, p, res, stream, 0x1p53);
 }
@@ -343,7 +343,7 @@ int vnp_snrmp(int64_t n, const float *x, int64_t incx, float p, float *res, void
     if (n > VNP_MAX_N) return -1;
     if (n > 0 && !x) return -2;
     if (incx == 0) return -3;
-    if (!(p > 0)) return -4;
+    if (!p_ok(p)) return -4;
     if (!res) return -5;
     return run_pnorm<float>(n, x, incx, p, res, stream, 0x1p24f);
 }

@@ -258,13 +258,14 @@ int schatten(int64_t m, int64_t n, const T *A, int64_t lda, double p, T *res, vo
         return p == 2.0 ? vnp_snrmf(k, s, 1, res, stream) : vnp_snrmp(k, s, 1, (float)p, res, stream);
 }
 
-int check(int64_t m, int64_t n, const void *A, int64_t lda, double p, const void *res)
+template <typename T>
+int check(int64_t m, int64_t n, const void *A, int64_t lda, T p, const void *res)
 {
     if (m < 0 || m > 0x7fffffff) return -1;
     if (n < 0 || n > 0x7fffffff) return -2;
     if (m > 0 && n > 0 && !A) return -3;
     if (lda < (m > 1 ? m : 1) || lda > 0x7fffffff) return -4;
-    if (!(p > 0)) return -5;
+    if (!vnp::p_ok(p)) return -5;
     if (!res) return -6;
     return 0;
 }

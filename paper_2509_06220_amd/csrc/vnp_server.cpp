@@ -161,6 +161,8 @@ struct vnp_server {
     std::vector<Slot> slots;
     std::thread worker;
     bool stop = false;
+    int waiters = 0;                 // threads blocked in vnp_server_wait
+    std::condition_variable cv_left;  // signalled when the last waiter leaves after stop
     // Bumped under mu whenever the batcher may have work (a request queued, a slot freed,
     // stop), and per slot whenever the slot's batch is in flight (or stop): the polled
     // change counters of the busy-poll phase.
@@ -416,7 +418,9 @@ int vnp_server_create(vnp_server **srv, const vnp_server_config *cfg)
     if (e == hipSuccess && cfg->pool_bytes > 0) e = hipMalloc(reinterpret_cast<void **>(&pool), (size_t)cfg->pool_bytes);
     s->pool.init(pool, (uint64_t)cfg->pool_bytes);
     const size_t cap = (size_t)cfg->max_batch;
-    const size_t desc_bytes = (4 * cap + 32) * 8;  // ptrs | lens | incs | item offsets (+1 per class)
+    // ptrs | lens | incs | item offsets (n_c + 1 per class): at most 3 cap + 2 cap words,
+    // since a batch of cap requests has at most cap (dtype, p) classes
+    const size_t desc_bytes = (5 * cap + 1) * 8;
     s->slots.resize((size_t)cfg->streams);
     s->flight_seq.reset(new (std::nothrow) std::atomic<uint64_t>[(size_t)cfg->streams]);
     if (!s->flight_seq) {
@@ -453,9 +457,21 @@ int vnp_server_destroy(vnp_server *s)
     {
         std::lock_guard<std::mutex> lk(s->mu);
         s->stop = true;
+        // requests not yet launched complete as cancelled (their waiters return)
+        const int64_t t = now_ns();
+        for (const Pending &p : s->pending) {
+            auto it = s->tickets.find(p.ticket);
+            if (it == s->tickets.end()) continue;
+            it->second.r.status = VNP_ECANCELED;
+            it->second.r.value = __builtin_nan("");
+            it->second.r.t_done_ns = t;
+            it->second.done = true;
+            s->st.cancelled += 1;
+        }
         s->pending.clear();
         s->work_seq.fetch_add(1, std::memory_order_release);
     }
+    s->cv_done.notify_all();
     s->cv_work.notify_all();
     if (s->worker.joinable()) s->worker.join();
     {
@@ -465,6 +481,12 @@ int vnp_server_destroy(vnp_server *s)
     s->cv_slots.notify_all();
     for (Slot &sl : s->slots)
         if (sl.done_thread.joinable()) sl.done_thread.join();  // in-flight batches complete first
+    {
+        // every ticket is complete now: wait until the blocked waiters have returned
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->cv_done.notify_all();
+        s->cv_left.wait(lk, [s] { return s->waiters == 0; });
+    }
     free_slots(s);
     delete s;
     return 0;
@@ -497,7 +519,7 @@ int vnp_server_submit(vnp_server *s, const vnp_request *req, uint64_t *ticket)
     int info = 0;
     if (req->dtype != VNP_F64 && req->dtype != VNP_F32)
         info = -1;
-    else if (!(req->p > 0))
+    else if (!(req->dtype == VNP_F32 ? vnp::p_ok((float)req->p) : vnp::p_ok(req->p)))
         info = -2;
     else if (req->n < 0 || req->n > VNP_MAX_N)
         info = -3;
@@ -542,10 +564,13 @@ static int take_result(vnp_server *s, uint64_t ticket, vnp_result *out, std::uni
             auto j = s->tickets.find(ticket);
             return j == s->tickets.end() || j->second.done;
         };
+        s->waiters += 1;
         if (timeout_us < 0)
             s->cv_done.wait(lk, ready);
         else
             s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready);
+        s->waiters -= 1;
+        if (s->stop && s->waiters == 0) s->cv_left.notify_all();
         it = s->tickets.find(ticket);
         if (it == s->tickets.end()) return VNP_ENOTFOUND;
     }

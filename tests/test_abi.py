@@ -1,5 +1,6 @@
 """The C-ABI library loads on a machine without a GPU and exports every declared symbol;
 the product path shares nothing with the oracle."""
+import math
 import os
 import re
 import subprocess
@@ -43,3 +44,29 @@ def test_product_does_not_reference_the_oracle():
 def test_bench_refuses_several_gpus():
     r = subprocess.run(["python", os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True)
     assert r.returncode != 0 and "one GPU" in r.stderr
+
+
+def test_p_domain_is_checked_before_any_device_work():
+    """p <= 0, NaN, or so small that RN(1/p) overflows the working precision is an
+    invalid argument (the node of Sect. 4 is built from RN(1/p)); these calls return
+    before touching the device, so a machine without a GPU can run them."""
+    import ctypes
+
+    vnp = pytest.importorskip("paper_2509_06220_amd")
+    L = vnp.lib()
+    fake = ctypes.c_void_p(256)  # never dereferenced: the argument check fails first
+    for p in (0.0, -1.0, math.nan, 1e-310, 2.0 ** -1025):
+        assert L.vnp_dnrmp(1, fake, 1, p, fake, None) == -4, p
+        assert L.vnp_dnrmp_batched(1, fake, 1, fake, p, fake, None) == -5, p
+        assert L.vnp_dnrmp_mat(1, 1, fake, 1, p, fake, None) == -5, p
+        assert L.vnp_dschatten(1, 1, fake, 1, p, fake, None) == -5, p
+    for p in (0.0, math.nan, 1e-39, 2.0 ** -129):  # 1/p beyond the binary32 range
+        assert L.vnp_snrmp(1, fake, 1, p, fake, None) == -4, p
+        assert L.vnp_snrmp_batched(1, fake, 1, fake, p, fake, None) == -5, p
+        assert L.vnp_snrmp_mat(1, 1, fake, 1, p, fake, None) == -5, p
+        assert L.vnp_sschatten(1, 1, fake, 1, p, fake, None) == -5, p
+    # plans check the descriptor's p in the plan's dtype
+    h = ctypes.c_void_p()
+    for dt, p in ((vnp.F64, 1e-310), (vnp.F32, 1e-39), (vnp.F64, -2.0)):
+        d = vnp._PlanDesc(dt, p, 1, 256, None, 1, 256, 256, 0)
+        assert L.vnp_plan_create(ctypes.byref(h), ctypes.byref(d), None) == -2, (dt, p)
