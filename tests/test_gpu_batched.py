@@ -209,3 +209,26 @@ def test_p_plan_outlives_finalize():
     torch.cuda.synchronize()
     assert torch.equal(first, ref) and torch.equal(again, ref)
     plan.close()
+
+
+@pytest.mark.parametrize("fmt,p", [("f64", 2.0), ("f32", 2.0), ("f64", 3.0)])
+def test_long_segment_multipass_finish(fmt, p):
+    """One segment of more than 512 runs (2^25 + 7 FP64 or 2^26 + 7 FP32 elements: 1024
+    runs of 4 tiles at the default shape) among about a hundred short ones: its run roots
+    are reduced by the finish kernel in several passes.  Bitwise equal to the plain call
+    and within the parity bound of the oracle."""
+    long_n = (1 << 25) + 7 if fmt == "f64" else (1 << 26) + 7
+    L = vnp_gen.log_uniform_lengths(100, 0, 13, seed=21)
+    L[40] = long_n
+    off = np.zeros(L.size + 1, dtype=np.int64)
+    off[1:] = np.cumsum(L)
+    xh = vnp_gen.host_fill(int(off[-1]), dtype=fmt, kind="u11exp", lo=-30, hi=30, seed=22)
+    x = to_dev(xh)
+    print(f"multi-pass finish {fmt} p={p}: {L.size} segments, long one {long_n}", flush=True)
+    r = vnp.nrm_batched(x, to_dev(off), p=p).cpu().numpy()
+    for s in range(L.size):
+        assert r[s] == _plain(x, off, s, p), s
+    for s in (40, 0, 39, 41, 99):
+        seg = xh[off[s]:off[s + 1]]
+        o = oracle.nrmf(seg, "A") if p == 2.0 else oracle.nrmp(seg, p)
+        assert_parity(r[s], o, max(seg.size, 1), fmt, f"segment {s}")

@@ -6,7 +6,7 @@ hypot) and the exact norm; the device-generated input is checked to be the host 
 p-norms at n = 2^28 against the binary128 reference, against the oracle where its node
 is cheap (p = 1), exact power-of-two scaling, and p = 2 against the Frobenius call.
 The oracle's A_p with a correctly rounded pow per node needs minutes at n = 2^28, so
-the other p are pinned to it at the smaller sizes of the regular parity tests."""
+the other p are pinned to it on the first 2^24 elements of the same recipe."""
 import math
 
 import numpy as np
@@ -90,6 +90,26 @@ def test_c2_full_size(p):
     # exact power-of-two scaling (no node crosses the subnormal or overflow range)
     xd.mul_(32.0)
     assert bits(vnp.nrmp(xd, p).item(), "f64") == bits(32.0 * g, "f64")
+
+
+@pytest.mark.parametrize("p", [1.5, 3.0, 4.5, 8.0])
+def test_c2_recipe_against_the_oracle_at_2p24(p):
+    """A_p (the recursion with Listing 5's node and a correctly rounded pow) on the first
+    2^24 elements of the C2 vector: the streaming kernel with runs of several tiles per
+    wave, within the parity bound; and the binary128 reference for both."""
+    r = vnp_gen.recipe("c2")
+    n = 1 << 24
+    xh = vnp_gen.host_fill(n, dtype="f64", kind=r["kind"], lo=r["lo"], hi=r["hi"], seed=r["seed"],
+                           stream=r["stream"])
+    xd = torch.from_numpy(xh).cuda()
+    print(f"C2 recipe p={p} at 2^24 against A_p", flush=True)
+    g = vnp.nrmp(xd, p).item()
+    o = float(oracle.nrmp(xh, p, "A"))
+    assert_parity(g, o, n, "f64", f"p={p}")
+    hi, lo = oracle.ref_pnorm(xh, p)
+    ref = hi + lo
+    print(f"  p={p}: GPU {abs(g - ref) / ref / eps('f64'):.3f} eps, A_p {abs(o - ref) / ref / eps('f64'):.3f} eps "
+          "from the binary128 reference", flush=True)
 
 
 def test_c2_p2_is_frobenius():
