@@ -81,19 +81,26 @@ def same(a, b):
     return a == b or (math.isnan(a) and math.isnan(b))
 
 
-def blocker(srv, n=1 << 28):
-    """A long FP64 p = 3 request (about a millisecond on the device) that keeps the server's
-    only stream busy while a burst queues up behind it; returns its buffer and request."""
+def blocker(srv, n=1 << 29):
+    """A long FP64 p = 3 request (well over a millisecond on the device) that keeps the
+    server's only stream busy while a burst queues up behind it; returns its buffer and
+    request."""
     buf = torch.empty(n, dtype=torch.float64, device="cuda")
     vnp_gen.dev_fill(buf, kind="u11", seed=77)
     torch.cuda.synchronize()
     return buf, vnp.Request(vnp.F64, 3.0, n, buf.data_ptr(), 1)
 
 
-def burst(srv, reqs):
-    """All requests submitted back to back from native code (arrival time 0 each)."""
+def burst(srv, reqs, blk=None):
+    """All requests submitted back to back from native code.  With a blocker, the blocker is
+    submitted first (it starts at once on the idle device) and the burst follows about 0.1 ms
+    later (the load generator's arrival times are relative to 2 ms after its start), so the
+    whole burst queues behind it and forms one batch."""
+    tk = srv.submit(blk.x, blk.n, blk.dtype, blk.p, blk.incx) if blk is not None else None
     arr = (vnp.Request * len(reqs))(*reqs)
-    lat, val, st, wall = vnp_gen.run_load(srv, np.zeros(len(reqs)), arr)
+    lat, val, st, wall = vnp_gen.run_load(srv, np.full(len(reqs), -0.0019 if blk is not None else 0.0), arr)
+    if tk is not None:
+        assert srv.wait(tk).status == 0
     return val, st
 
 
@@ -230,7 +237,7 @@ def test_many_classes_in_one_batch():
     63 requests with distinct p, queued behind a blocker, launch as one batch."""
     srv = vnp.Server(pool_bytes=1 << 28, max_batch=63, streams=1, max_wait_us=200000)
     buf, blk = blocker(srv)
-    reqs, meta = [blk], []
+    reqs, meta = [], []
     for i in range(63):
         dtype = vnp.F64 if i % 3 else vnp.F32
         p = 1.03 + 0.11 * i  # 63 distinct p, none of 1, 2 or inf
@@ -241,15 +248,15 @@ def test_many_classes_in_one_batch():
         reqs.append(vnp.Request(dtype, p, n, ptr, incx))
         meta.append((ptr, n, dtype, p, incx))
     torch.cuda.synchronize()
-    val, st = burst(srv, reqs)
+    val, st = burst(srv, reqs, blk)
     assert np.all(st == 0)
     stats = srv.stats()
     print("many classes:", stats, flush=True)
     assert stats["max_batch_seen"] > 32
     for i, (ptr, n, dtype, p, incx) in enumerate(meta):
         r = plain(ptr, n, dtype, p, incx)
-        assert same(val[i + 1], r), (i, val[i + 1], r)
-        check_oracle(val[i + 1], n, dtype, p, incx, 11, i, "distinct-p batch")
+        assert same(val[i], r), (i, val[i], r)
+        check_oracle(val[i], n, dtype, p, incx, 11, i, "distinct-p batch")
     srv.close()
     del buf
 
@@ -261,7 +268,7 @@ def test_long_requests_in_a_mixed_batch():
     buf, blk = blocker(srv)
     specs = [(vnp.F64, (1 << 24) + 5, 2.0, 1), (vnp.F64, (1 << 24) + 5, 3.0, -1), (vnp.F32, (1 << 25) + 3, 2.0, 1),
              (vnp.F64, 5000, 2.0, 1), (vnp.F32, 777, 3.0, 2), (vnp.F64, 100000, 2.0, -2)]
-    reqs, meta = [blk], []
+    reqs, meta = [], []
     for i, (dtype, n, p, incx) in enumerate(specs):
         esz = 8 if dtype == vnp.F64 else 4
         ptr = srv.alloc(((n - 1) * abs(incx) + 1) * esz)
@@ -270,15 +277,15 @@ def test_long_requests_in_a_mixed_batch():
         reqs.append(vnp.Request(dtype, p, n, ptr, incx))
         meta.append((ptr, n, dtype, p, incx))
     torch.cuda.synchronize()
-    val, st = burst(srv, reqs)
+    val, st = burst(srv, reqs, blk)
     assert np.all(st == 0)
     stats = srv.stats()
     print("mixed long batch:", stats, flush=True)
     assert stats["max_batch_seen"] == len(specs)  # the burst formed one batch behind the blocker
     for i, (ptr, n, dtype, p, incx) in enumerate(meta):
         print(f"  request {i}: n={n} dtype={dtype} p={p} incx={incx}", flush=True)
-        assert same(val[i + 1], plain(ptr, n, dtype, p, incx)), i
-        check_oracle(val[i + 1], n, dtype, p, incx, 13, i, "mixed long batch")
+        assert same(val[i], plain(ptr, n, dtype, p, incx)), i
+        check_oracle(val[i], n, dtype, p, incx, 13, i, "mixed long batch")
     srv.close()
     del buf
 
