@@ -93,10 +93,14 @@ def blocker(srv, n=1 << 29):
 
 def burst(srv, reqs, blk=None):
     """All requests submitted back to back from native code.  With a blocker, the blocker is
-    submitted first (it starts at once on the idle device) and the burst follows about 0.1 ms
-    later (the load generator's arrival times are relative to 2 ms after its start), so the
-    whole burst queues behind it and forms one batch."""
-    tk = srv.submit(blk.x, blk.n, blk.dtype, blk.p, blk.incx) if blk is not None else None
+    submitted first and, once it is in flight, the burst follows about 0.1 ms later (the
+    load generator's arrival times are relative to 2 ms after its start), so the whole burst
+    queues behind it and forms one batch."""
+    tk = None
+    if blk is not None:
+        tk = srv.submit(blk.x, blk.n, blk.dtype, blk.p, blk.incx)
+        while srv.stats()["in_flight"] == 0:  # the blocker is on the device before the burst starts
+            time.sleep(0.00002)
     arr = (vnp.Request * len(reqs))(*reqs)
     lat, val, st, wall = vnp_gen.run_load(srv, np.full(len(reqs), -0.0019 if blk is not None else 0.0), arr)
     if tk is not None:
