@@ -77,6 +77,18 @@ extern "C" {
 int vnp_dnrmf(int64_t n, const double *x, int64_t incx, double *res, void *stream);
 int vnp_snrmf(int64_t n, const float *x, int64_t incx, float *res, void *stream);
 
+/* vnp_dnrmf for callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the same kernels and bits as vnp_dnrmf,
+ * with the block roots kept in a fixed device array of VNP_NOALLOC_MAX_ROOTS doubles (64 KiB,
+ * one per device, held until the process ends) instead of a per-stream workspace.  It never
+ * calls hipMalloc or hipFree.  Every call on a device shares that device's array: calls
+ * that overlap on one device (another stream, another thread) race and must be serialized by
+ * the caller.  With the automatic launch shape every n <= VNP_MAX_N fits (at most 4096 roots
+ * on a 256-CU device); a shape forced by vnp_set_launch_shape that needs more roots -> -1.
+ * Other errors as vnp_dnrmf. */
+#define VNP_NOALLOC_MAX_ROOTS 8192
+int vnp_dnrmf_noalloc(int64_t n, const double *x, int64_t incx, double *res, void *stream);
+
 /* p-norm.  p = 1 uses |a| + |b| nodes (Eq. (vp1)); p = +inf, and p at or above the
  * cutoff of Sect. 4 (2^53 for D, 2^24 for S), use max(|a|, |b|) (Eq. (vpI)); p = 2 uses
  * the Frobenius node; other p > 0 use the node of Listing 5 (0 < p < 1 gives the

@@ -44,6 +44,7 @@ def lib():
         sig = {
             "vnp_dnrmf": [i64, vp, i64, vp, vp],
             "vnp_snrmf": [i64, vp, i64, vp, vp],
+            "vnp_dnrmf_noalloc": [i64, vp, i64, vp, vp],
             "vnp_dnrmp": [i64, vp, i64, d, vp, vp],
             "vnp_snrmp": [i64, vp, i64, f, vp, vp],
             "vnp_dnrmf_batched": [i64, vp, i64, vp, vp, vp],

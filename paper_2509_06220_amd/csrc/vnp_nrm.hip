@@ -201,11 +201,29 @@ static void launch(const Node &nd, bool fast, dim3 grid, dim3 block, hipStream_t
         hipLaunchKernelGGL((nrm_finish_kernel<Node>), dim3(1), dim3(256), 0, st, nd, roots, (int64_t)grid.x, res);
 }
 
+// The roots buffer of one call: the stream's workspace (fixed == nullptr), or the
+// caller's fixed buffer of fixed_cap elements, which must hold every root (else -1).
+template <typename T>
+static int roots_buffer(void *stream, int64_t count, T *fixed, int64_t fixed_cap, T **out)
+{
+    if (fixed) {
+        if (count > fixed_cap) return -1;
+        *out = fixed;
+        return 0;
+    }
+    Workspace *ws = nullptr;
+    const int rc = get_workspace(stream, sizeof(T) * (size_t)count, &ws);
+    if (rc) return rc;
+    *out = static_cast<T *>(ws->roots);
+    return 0;
+}
+
 // n logical elements, element 0 at base, address map sd; fast: contiguous and naturally
 // aligned (vector loads).
 template <class Node>
 static int run_norm_map(const Node &nd, int64_t n, const typename Node::T *base, Stride sd, bool fast,
-                        typename Node::T *res, void *stream)
+                        typename Node::T *res, void *stream, typename Node::T *fixed = nullptr,
+                        int64_t fixed_cap = 0)
 {
     using T = typename Node::T;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -217,10 +235,9 @@ static int run_norm_map(const Node &nd, int64_t n, const typename Node::T *base,
     const int64_t ntiles = (n + TE - 1) / TE;
     if (ntiles < (int64_t)cu_count() * 4 && g_force_wpb == 0 && g_force_lwt < 0) {
         // small vector: eight waves per tile (see nrm_tile_kernel)
-        Workspace *ws = nullptr;
-        int rc = get_workspace(stream, sizeof(T) * (size_t)ntiles, &ws);
+        T *roots = nullptr;
+        const int rc = roots_buffer<T>(stream, ntiles, fixed, fixed_cap, &roots);
         if (rc) return rc;
-        T *roots = static_cast<T *>(ws->roots);
         if (fast)
             hipLaunchKernelGGL((nrm_tile_kernel<Node, true>), dim3((unsigned)ntiles), dim3(TILE_WAVES * WAVE), 0, st,
                                nd, base, n, sd, roots, res);
@@ -237,22 +254,51 @@ static int run_norm_map(const Node &nd, int64_t n, const typename Node::T *base,
     const Shape s = choose_shape(ntiles);
     const int64_t per_block = (int64_t)s.wpb << s.lwt;
     const int64_t nblocks = (ntiles + per_block - 1) / per_block;
-    Workspace *ws = nullptr;
-    int rc = get_workspace(stream, sizeof(T) * (size_t)nblocks, &ws);
+    T *roots = nullptr;
+    const int rc = roots_buffer<T>(stream, nblocks, fixed, fixed_cap, &roots);
     if (rc) return rc;
-    launch(nd, fast, dim3((unsigned)nblocks), dim3((unsigned)(s.wpb * WAVE)), st, base, n, sd, ntiles, s.lwt,
-           static_cast<T *>(ws->roots), res);
+    launch(nd, fast, dim3((unsigned)nblocks), dim3((unsigned)(s.wpb * WAVE)), st, base, n, sd, ntiles, s.lwt, roots,
+           res);
     return (int)hipGetLastError();
 }
 
 template <class Node>
 static int run_norm(const Node &nd, int64_t n, const typename Node::T *x, int64_t incx, typename Node::T *res,
-                    void *stream)
+                    void *stream, typename Node::T *fixed = nullptr, int64_t fixed_cap = 0)
 {
     using T = typename Node::T;
     const T *base = incx >= 0 || n <= 0 ? x : x + (n - 1) * (-incx);
     const bool fast = incx == 1 && ((uintptr_t)x % sizeof(T)) == 0;
-    return run_norm_map(nd, n, base, real_stride(incx), fast, res, stream);
+    return run_norm_map(nd, n, base, real_stride(incx), fast, res, stream, fixed, fixed_cap);
+}
+
+// ---------------------------------------------------------------------------------
+// Allocation-free DNRMF: the block (or tile) roots of a call live in a fixed device array
+// instead of the per-stream workspace.  Host code never passes the array's name (a host
+// stand-in) to a kernel: it uses the device address taken once per device.
+// ---------------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[VNP_NOALLOC_MAX_ROOTS];
+
+constexpr int SCRATCH_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[SCRATCH_DEVICES] = {};
+
+// The current device's copy of `scratch` (looked up on the first call on that device).
+static int scratch_ptr(double **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return (int)e;
+    if (dev < 0 || dev >= SCRATCH_DEVICES) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return (int)e;
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return 0;
 }
 
 // Frobenius norm of n complex elements (interleaved re, im) with stride incz (in complex
@@ -317,6 +363,18 @@ int vnp_dnrmf(int64_t n, const double *x, int64_t incx, double *res, void *strea
     if (incx == 0) return -3;
     if (!res) return -4;
     return run_norm(HypNode<double>{}, n, x, incx, res, stream);
+}
+
+int vnp_dnrmf_noalloc(int64_t n, const double *x, int64_t incx, double *res, void *stream)
+{
+    if (n > VNP_MAX_N) return -1;
+    if (n > 0 && !x) return -2;
+    if (incx == 0) return -3;
+    if (!res) return -4;
+    double *roots = nullptr;
+    const int rc = scratch_ptr(&roots);
+    if (rc) return rc;
+    return run_norm(HypNode<double>{}, n, x, incx, res, stream, roots, (int64_t)VNP_NOALLOC_MAX_ROOTS);
 }
 
 int vnp_snrmf(int64_t n, const float *x, int64_t incx, float *res, void *stream)
