@@ -27,20 +27,36 @@ import numpy as np
 from . import bounds, exact  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB = os.path.join(_HERE, "libvnp_oracle.so")
 SRC = os.path.join(_HERE, "vnp_oracle.c")
+PLAIN_LIB = os.path.join(_HERE, "libvnp_oracle.so")
+SANITIZED_LIB = os.path.join(_HERE, "libvnp_oracle_asan.so")
+# VNP_ORACLE_SANITIZED=1 loads the AddressSanitizer + UndefinedBehaviorSanitizer build
+# (the process must preload the ASan runtime; see tests/test_oracle_sanitized.py)
+LIB = SANITIZED_LIB if os.environ.get("VNP_ORACLE_SANITIZED") == "1" else PLAIN_LIB
 
 CFLAGS = ["-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-std=gnu11"]
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g"]
 LIBS = ["-lquadmath", "-lm", "-ldl"]
+
+
+def _compile(out, extra):
+    tmp = out + ".tmp"
+    subprocess.check_call(["gcc", *CFLAGS, *extra, SRC, "-o", tmp, *LIBS])
+    os.replace(tmp, out)
 
 
 def build(force: bool = False) -> str:
     """Compile the C oracle with gcc (no SIMD options, no fast-math)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, SRC, "-o", tmp, *LIBS])
-        os.replace(tmp, LIB)
+        _compile(LIB, SANITIZE if LIB == SANITIZED_LIB else [])
     return LIB
+
+
+def build_sanitized(force: bool = False) -> str:
+    """The same oracle built with AddressSanitizer and UndefinedBehaviorSanitizer."""
+    if force or not os.path.exists(SANITIZED_LIB) or os.path.getmtime(SANITIZED_LIB) < os.path.getmtime(SRC):
+        _compile(SANITIZED_LIB, SANITIZE)
+    return SANITIZED_LIB
 
 
 _lib = None
