@@ -26,8 +26,9 @@
  *     the ABI.
  *   - n <= 0 (or nseg segments of length 0) give a result of +0.
  *   - "p invalid" below: p <= 0, p NaN, or p so small that 1/p rounded once in the
- *     working precision overflows (p below about 2^-1024 for D, 2^-128 for S; the node of
- *     Sect. 4 is built from RN(1/p)).  A binary32 call rounds p to binary32 first.
+ *     working precision exceeds 2^1000 (D) or overflows (S): p below about 2^-1000 for D,
+ *     2^-128 for S (the node of Sect. 4 is built from RN(1/p)).  A binary32 call rounds p
+ *     to binary32 first.
  *   - Special values: any NaN element gives NaN; otherwise any infinite element gives
  *     +inf; otherwise the tree result, which is +inf only if the norm overflows.
  *   - Calls on different streams may run concurrently; each (device, stream) pair gets

@@ -774,7 +774,7 @@ static int plan_lp_node(PlanImpl &P, T p, LpNode<T> *nd)
     int rc = make_lp_node<T>(p, nd);
     if (rc) return rc;
     if (!P.lp_rr) {
-        const size_t bytes = 2 * LP_TAB_N * sizeof(double);
+        const size_t bytes = 2 * LP_POW_N * sizeof(double);
         hipError_t e = hipMalloc(reinterpret_cast<void **>(&P.lp_rr), bytes);
         if (e == hipSuccess) e = hipMemcpy(P.lp_rr, nd->rr, bytes, hipMemcpyDeviceToDevice);
         if (e != hipSuccess) return (int)e;

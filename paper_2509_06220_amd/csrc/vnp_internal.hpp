@@ -85,12 +85,13 @@ struct MaxNode<float> {
 };
 
 // The p values the p-norm calls accept: p > 0 (not NaN) whose reciprocal, rounded once in
-// the working precision, is finite (the node is built from RN(1/p), Sect. 4); a p below
-// that (about 2^-1024 in binary64, 2^-128 in binary32) is an invalid argument.
+// the working precision, is at most 2^1000 in binary64 (the node squares its power of Z at
+// most 1000 times) and finite in binary32 (the node is built from RN(1/p), Sect. 4); a p
+// below that (about 2^-1000 in binary64, 2^-128 in binary32) is an invalid argument.
 template <typename T>
 __host__ __device__ inline bool p_ok(T p)
 {
-    return p > T(0) && __builtin_isfinite(T(1) / p);
+    return p > T(0) && T(1) / p <= T(sizeof(T) == 8 ? 0x1p1000 : 0x1.fffffep127);
 }
 
 // Rows per load group (one group is in flight per wave while the previous one is

@@ -7,32 +7,39 @@
 // and RN32(1/p) and evaluates the node in binary64, rounding the node value to binary32.
 //
 // The two powers are evaluated on the ranges the node produces, without the
-// general-purpose library routines and without a division:
+// general-purpose library routines and without a division, from tables in LDS:
 //   S = 2^((p/2) log2 Q),  log2 Q = (e_m - e_M) + log2 f_m - log2 f_M  (frexp parts f in
-//   [1/2, 1), exponents e).  log2 f: the top LP_TAB_BITS fraction bits of f pick c_j ~ 1/f
-//   and l_j = log2(2 / c_j) from a table in LDS; log2 f = (l_j - 1) + log2(1 + t) with
-//   t = fma(f, c_j, -1), |t| <= 1.01 * 2^-8, and log2(1 + t) = t g(t), g of degree 5.
-//   2^y splits y = k + f, |f| <= 1/2, evaluates 2^f by a degree-11 polynomial in f and
-//   scales by 2^k.
+//   [1/2, 1), exponents e).  log2 f: the top LP_LOG_BITS fraction bits of f pick c_j ~ 1/f
+//   and l_j = log2(2 / c_j); log2 f + 1 = l_j + t g(t), t = fma(f, c_j, -1), |t| <= 1.01 *
+//   2^-11, g of degree 3, evaluated as fma(t, g, l_j).
+//   2^(y/128) for y = 128 (p/2) log2 Q: y = 128 k + j + u with integers k, j in [0, 128)
+//   and |u| <= 1/2 (rounding y to an integer by adding 1.5 * 2^52, whose low word then
+//   holds it), 2^(y/128) = 2^k T_j (1 + u H(u)), T_j = RN(2^(j/128)), H of degree 4.
 //   C = Z^a, a = RN(1/p), Z in [1, 2]: with a = a' 2^s, a' <= 2, C = (Z^a')^(2^s).  The top
-//   LP_TAB_BITS fraction bits of Z pick c'_j = RN(2^7 / (2^7 + j)) (the reciprocal of the
+//   LP_POW_BITS fraction bits of Z pick c'_j = RN(512 / (512 + j)) (the reciprocal of the
 //   interval's left end), R_j = (1/c'_j)^a' and rho_j = R_j - 1 (both rounded from an
 //   extended-precision value; one device table per (device, p), built and uploaded by
-//   make_lp_node on first use); with t = fma(Z, c'_j, -1) in
-//   [0, 2^-7), Z^a' = R_j (1 + t)^a' and (1 + t)^a' = 1 + u, u = t (b_1 + b_2 t + ... +
-//   b_7 t^6) with the binomial coefficients b_k of a'.  Then Z^a' = 1 + fma(u, R_j, rho_j):
-//   Z = 1 gives exactly 1, and R_j's rounding touches only the small product.
+//   make_lp_node on first use); with t = fma(Z, c'_j, -1) in [0, 2^-9),
+//   Z^a' = R_j (1 + t)^a' and (1 + t)^a' = 1 + u, u = t (b_1 + b_2 t + ... + b_5 t^4)
+//   with the binomial coefficients b_k of a'.  Then Z^a' = 1 + w, w = fma(u, R_j, rho_j),
+//   so R_j's rounding touches only the small product; each squaring maps w to w (w + 2);
+//   and the node is fma(M, w, M), one rounding of M (1 + w).
 // (Coefficients and tables: Chebyshev fits and 60-digit values written by lp_coeffs.py.)
 //
-// Errors: the log2 table values carry 2^-54 absolute, the polynomials 2^-61.7
-// (log2(1 + t), absolute) and 2^-55.5 (2^f, relative); the binomial series omits less than
-// 2^-61.9.  An absolute error d in log2 Q changes C by at most (ln 2 / 2) d relatively,
-// whatever p is (the error of S^2 is weighted by S^2 / (p (1 + S^2)) in C); each squaring
-// doubles the relative error of Z^a', so p < 1/2 costs about 2^s ulps more.
+// Errors: the log2 table values carry 2^-54 absolute and the two fma(t, g, l_j) 2^-54
+// each, g 2^-59.6 (absolute), 1 + u H(u) 2^-62.8 and T_j 2^-53 (relative); the binomial
+// series omits less than 2^-59.4.  An absolute error d in log2 Q changes C by at most
+// (ln 2 / 2) d relatively, whatever p is (the error of S^2 is weighted by
+// S^2 / (p (1 + S^2)) in C); each squaring doubles the relative error of Z^a', so p < 1/2
+// costs about 2^s ulps more.
 //
-// Special operands: M is taken as the larger bit pattern, so a NaN operand becomes M and
-// the node returns NaN; an infinite M (and no NaN) returns +inf; m = 0 returns M.  Their
-// intermediate values are finite or NaN and are discarded by the final select.
+// Special operands: M and m come from v_max_f64 / v_min_f64 (the non-NaN operand if one
+// is NaN); w is finite and positive for every input (a NaN or infinite Z is clamped into
+// [1, 2) before the table lookup, and rho_0 = 2^-1074 instead of 0, whose s squarings stay
+// below 2^-1074 * 2^(s + 1) < 2^-54 for s <= 1000), so fma(M, w, M) is +inf for an
+// infinite M and equals M whenever w < 2^-54; a NaN operand turns w into a quiet NaN.
+// m = 0 (Q = 0) clears the high word of S: what is left is below 2^-1042, its square
+// vanishes, Z = 1, w = 2^(s - 1074) at most, and node(M, 0) = M exactly.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -48,180 +55,180 @@
 
 namespace vnp {
 
-constexpr int LP_TAB_N = 1 << LP_TAB_BITS;
+constexpr int LP_LOG_N = 1 << LP_LOG_BITS;
+constexpr int LP_EXP_N = 1 << LP_EXP_BITS;
+constexpr int LP_POW_N = 1 << LP_POW_BITS;
+constexpr int LP_B_N = 8;  // binomial coefficient slots (LP_POW_TERMS used)
+constexpr double LP_RHO0 = 0x1p-1074;  // rho_0 (see above)
 
-// The tables in LDS: one copy per block, filled by lp_table_fill at kernel entry.
-__device__ __forceinline__ double2 *lp_table()
+// The tables in LDS, one copy per block, filled by lp_table_fill at kernel entry.
+__device__ __forceinline__ double2 *lp_log_lds()  // {c_j, l_j}
 {
-    __shared__ double2 tab[LP_TAB_N];
+    __shared__ double2 tab[LP_LOG_N];
     return tab;
 }
-// c'_j, R_j, rho_j, then b_1 .. b_7 (and a zero), then the 2^f coefficients of f^11 .. f^1,
-// then the log2(1 + t) / t coefficients of t^5 .. t^0
-constexpr int LP_EXP_OFF = 3 * LP_TAB_N + 8;
-constexpr int LP_LOG_OFF = LP_EXP_OFF + 11;
-__device__ __forceinline__ double *lp_ptable()
+__device__ __forceinline__ double *lp_exp_lds()  // T_j
 {
-    __shared__ double tab[LP_LOG_OFF + 6];
+    __shared__ double tab[LP_EXP_N];
+    return tab;
+}
+struct PowEntry {
+    double R, rho, c, pad;
+};
+__device__ __forceinline__ PowEntry *lp_pow_lds()  // {R_j, rho_j, c'_j}
+{
+    __shared__ PowEntry tab[LP_POW_N];
+    return tab;
+}
+// Polynomial coefficients: g (4), H (5), then the binomial coefficients b_1 .. b_5 (and
+// zeros).  Read at one address in all lanes: as scalar operands they would exhaust the
+// scalar registers, and two scalar operands of one fma cost an extra vector move.
+constexpr int LP_G_OFF = 0, LP_H_OFF = 4, LP_BC_OFF = 9;
+__device__ __forceinline__ double *lp_coef_lds()
+{
+    __shared__ double tab[LP_BC_OFF + LP_B_N];
     return tab;
 }
 
 // Every thread of the block calls this before the first node evaluation.  rr: the per-p
-// device table (R_0 .. R_127, rho_0 .. rho_127); b: the binomial coefficients.
+// device table (R_0 .. R_511, rho_0 .. rho_511); b: the binomial coefficients.
 __device__ __forceinline__ void lp_table_fill(const double *rr, const double *b)
 {
-    double2 *tab = lp_table();
-    double *pt = lp_ptable();
-    for (int i = threadIdx.x; i < LP_TAB_N; i += blockDim.x) {
-        tab[i] = make_double2(lp_tab_src[i][0], lp_tab_src[i][1]);
-        pt[i] = lp_ptab_src[i];
-        pt[LP_TAB_N + i] = rr[i];
-        pt[2 * LP_TAB_N + i] = rr[LP_TAB_N + i];
-    }
-    if (threadIdx.x < 8) pt[3 * LP_TAB_N + threadIdx.x] = b[threadIdx.x];
-    if (threadIdx.x < 11) {
-        // 2^f on |f| <= 1/2, degree 11 (Chebyshev fit, relative error 2^-55.5), f^11 first
-        constexpr double E[11] = {0x1.e9ec1fcb69a7fp-32, 0x1.e6228acd1c6e5p-28, 0x1.b524ebd13a55fp-24,
-                                  0x1.62bfc2c86d700p-20, 0x1.ffcbfc6da6ed1p-17, 0x1.430913112c61bp-13,
-                                  0x1.5d87fe78a3f9cp-10, 0x1.3b2ab6fb9f1a5p-7,  0x1.c6b08d704a0c6p-5,
-                                  0x1.ebfbdff82c5aep-3,  0x1.62e42fefa39efp-1};
-        pt[LP_EXP_OFF + threadIdx.x] = E[threadIdx.x];
-    }
-    if (threadIdx.x < 6) {
-        // log2(1 + t) = t g(t), |t| <= 1.01 * 2^-8, g of degree 5 (absolute error 2^-61.7)
-        constexpr double G[6] = {-0x1.ec72d2e6fb6e9p-3, 0x1.277807fe93552p-2, -0x1.715476524c17ep-2,
-                                 0x1.ec709dc324b6cp-2,  -0x1.71547652b82fep-1, 0x1.71547652b82fep+0};
-        pt[LP_LOG_OFF + threadIdx.x] = G[threadIdx.x];
-    }
+    double2 *lt = lp_log_lds();
+    double *et = lp_exp_lds();
+    PowEntry *pt = lp_pow_lds();
+    for (int i = threadIdx.x; i < LP_LOG_N; i += blockDim.x) lt[i] = make_double2(lp_log_src[i][0], lp_log_src[i][1]);
+    for (int i = threadIdx.x; i < LP_EXP_N; i += blockDim.x) et[i] = lp_exp_src[i];
+    for (int i = threadIdx.x; i < LP_POW_N; i += blockDim.x)
+        pt[i] = PowEntry{rr[i], rr[LP_POW_N + i], lp_pow_src[i], 0.0};
+    double *cf = lp_coef_lds();
+    if (threadIdx.x < 4) cf[LP_G_OFF + threadIdx.x] = lp_log_g[threadIdx.x];
+    if (threadIdx.x < 5) cf[LP_H_OFF + threadIdx.x] = lp_exp_h[threadIdx.x];
+    if (threadIdx.x < LP_B_N) cf[LP_BC_OFF + threadIdx.x] = b[threadIdx.x];
     __syncthreads();
 }
 
-// log2 f - (l_j - 1) for f in [1/2, 1), and l_j through `l`.
-__device__ __forceinline__ double log2_part(double f, double &l)
+// log2 f + 1 for f in [1/2, 1).
+__device__ __forceinline__ double log2_p1(double f)
 {
     const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(f) >> 32);
-    const double2 e = lp_table()[(hi >> (20 - LP_TAB_BITS)) & (LP_TAB_N - 1)];
-    l = e.y;
+    const double2 e = lp_log_lds()[(hi >> (20 - LP_LOG_BITS)) & (LP_LOG_N - 1)];
     const double t = __builtin_fma(f, e.x, -1.0);
-    const double *G = lp_ptable() + LP_LOG_OFF;  // the same address in every lane (see exp2_poly)
+    const double *G = lp_coef_lds() + LP_G_OFF;
     double g = G[0];
 #pragma unroll
-    for (int i = 1; i < 6; ++i) g = __builtin_fma(g, t, G[i]);
-    return t * g;
+    for (int i = 1; i < 4; ++i) g = __builtin_fma(g, t, G[i]);
+    return __builtin_fma(t, g, e.y);
 }
 
-// 2^y for finite y in [-2100, 2100] (0 and +inf beyond the binary64 range).  The
-// coefficients are read from LDS (lp_table_fill): as immediates they exhaust the scalar
-// registers of the streaming kernel, and the compiler then rebuilds each 64-bit
-// coefficient with two vector moves at every use (about a fifth of the node's VALU
-// instructions); from LDS they are loaded once into vector registers.
-__device__ __forceinline__ double exp2_poly(double y)
+// 2^(y/128) for y in [-2100 * 128, 0] (y = +inf gives NaN, which the caller absorbs).
+__device__ __forceinline__ double exp2_tab(double y)
 {
-    const double k = __builtin_rint(y);
-    const double f = y - k;  // exact, |f| <= 1/2
-    const double *E = lp_ptable() + LP_EXP_OFF;  // the same address in every lane
-    double t = E[0];
+    // y + 1.5 * 2^52 holds round(y) in its low word (|y| < 2^31)
+    const double big = y + 0x1.8p52;
+    const int k = (int)(uint32_t)(uint64_t)__double_as_longlong(big);
+    const double u = y - (big - 0x1.8p52);  // exact, |u| <= 1/2
+    const double T = lp_exp_lds()[k & (LP_EXP_N - 1)];
+    const double *Hc = lp_coef_lds() + LP_H_OFF;
+    double h = Hc[0];
 #pragma unroll
-    for (int i = 1; i < 11; ++i) t = __builtin_fma(t, f, E[i]);
-    t = __builtin_fma(t, f, 1.0);
-    return __builtin_amdgcn_ldexp(t, (int)k);
+    for (int i = 1; i < 5; ++i) h = __builtin_fma(h, u, Hc[i]);
+    return __builtin_amdgcn_ldexp(__builtin_fma(T, u * h, T), k >> LP_EXP_BITS);
 }
 
-// Z^a for Z in [1, 2] (a = a' 2^s, see above); b: the binomial coefficients b_1 .. b_7.
-__device__ __forceinline__ double pow_z(double Z, int sq, const double *b)
+// w = Z^a - 1 for Z in [1, 2] (a = a' 2^s, see above).
+__device__ __forceinline__ double pow_z_m1(double Z, int sq)
 {
+    const double *b = lp_coef_lds() + LP_BC_OFF;
     const double Zc = __builtin_fmin(Z, 0x1.fffffffffffffp0);  // Z = 2 as its predecessor: within Z's rounding
     const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(Zc) >> 32);
-    const uint32_t j = (hi >> (20 - LP_TAB_BITS)) & (LP_TAB_N - 1);
-    const double *pt = lp_ptable();
-    const double t = __builtin_fma(Zc, pt[j], -1.0);  // in [0, 2^-7)
-    double q = b[6];
-    q = __builtin_fma(q, t, b[5]);
-    q = __builtin_fma(q, t, b[4]);
+    const PowEntry &e = lp_pow_lds()[(hi >> (20 - LP_POW_BITS)) & (LP_POW_N - 1)];
+    const double t = __builtin_fma(Zc, e.c, -1.0);  // in [0, 2^-9)
+    double q = b[4];
     q = __builtin_fma(q, t, b[3]);
     q = __builtin_fma(q, t, b[2]);
     q = __builtin_fma(q, t, b[1]);
     q = __builtin_fma(q, t, b[0]);
-    double C = 1.0 + __builtin_fma(t * q, pt[LP_TAB_N + j], pt[2 * LP_TAB_N + j]);
-    for (int i = 0; i < sq; ++i) C *= C;
-    return C;
+    double w = __builtin_fma(t * q, e.R, e.rho);
+    for (int i = 0; i < sq; ++i) w = w * (w + 2.0);
+    return w;
 }
 
-__device__ __forceinline__ double lp_core(double a, double b, double half_p, int sq, const double *bc)
+// The node on |a|, |b| (ABS: a leaf, whose operands carry signs; otherwise a, b >= 0),
+// NaN and infinities as above; hp128 = 128 RN(p/2) (exact).
+template <bool ABS>
+__device__ __forceinline__ double lp_core(double a, double b, double hp128, int sq)
 {
-    const uint64_t ia = (uint64_t)__double_as_longlong(a), ib = (uint64_t)__double_as_longlong(b);
-    const double M = __longlong_as_double((long long)(ia > ib ? ia : ib));
-    const double m = __longlong_as_double((long long)(ia > ib ? ib : ia));
-    double lM, lm;
-    const double pM = log2_part(__builtin_amdgcn_frexp_mant(M), lM);
-    const double pm = log2_part(__builtin_amdgcn_frexp_mant(m), lm);
+    // v_max_f64 / v_min_f64 directly, the absolute values as operand modifiers: as fmax /
+    // fmin the compiler first canonicalizes each operand (two more instructions), which only
+    // matters for NaN operands, restored below
+    double M, m;
+    if constexpr (ABS) {
+        asm("v_max_f64 %0, |%1|, |%2|" : "=v"(M) : "v"(a), "v"(b));
+        asm("v_min_f64 %0, |%1|, |%2|" : "=v"(m) : "v"(a), "v"(b));
+    } else {
+        asm("v_max_f64 %0, %1, %2" : "=v"(M) : "v"(a), "v"(b));
+        asm("v_min_f64 %0, %1, %2" : "=v"(m) : "v"(a), "v"(b));
+    }
+    const bool nan = __builtin_isunordered(a, b);
+    const double hM = log2_p1(__builtin_amdgcn_frexp_mant(M));
+    const double hm = log2_p1(__builtin_amdgcn_frexp_mant(m));
     const int e = __builtin_amdgcn_frexp_exp(m) - __builtin_amdgcn_frexp_exp(M);
-    const double lq = (double)e + ((lm - lM) + (pm - pM));  // log2 Q <= 0
-    const double S = exp2_poly(__builtin_fmax(half_p * lq, -2100.0));
-    const double Z = __builtin_fma(S, S, 1.0);  // in [1, 2]
-    const double C = pow_z(Z, sq, bc);
-    const bool regular = m > 0.0 && M < __builtin_inf();  // also false for a NaN M
-    return regular ? M * C : M;
+    const double lq = (double)e + (hm - hM);  // log2 Q <= 0
+    const double S = exp2_tab(__builtin_fmax(hp128 * lq, -2100.0 * 128));
+    const uint64_t sb = (uint64_t)__double_as_longlong(S);
+    const uint32_t shi = m > 0.0 ? (uint32_t)(sb >> 32) : 0u;  // m = 0: S below 2^-1042
+    const double Sm = __longlong_as_double((long long)(((uint64_t)shi << 32) | (sb & 0xffffffffu)));
+    const uint64_t wb = (uint64_t)__double_as_longlong(pow_z_m1(__builtin_fma(Sm, Sm, 1.0), sq));
+    const uint32_t whi = nan ? 0x7ff80000u : (uint32_t)(wb >> 32);  // a NaN operand: w is a quiet NaN
+    return __builtin_fma(M, __longlong_as_double((long long)(((uint64_t)whi << 32) | (wb & 0xffffffffu))), M);
 }
 
-// The evaluation part of the p node: p/2 and s, with every table read from LDS.  Device
-// functions that are not inlined receive this part only (node_eval).
+// The evaluation part of the p node: 128 RN(p/2) and s, with every table read from LDS.
+// Device functions that are not inlined receive this part only (node_eval).
 template <typename T>
 struct LpEval;
-
-__device__ __forceinline__ const double *lp_binom_lds() { return lp_ptable() + 3 * LP_TAB_N; }
 
 template <>
 struct LpEval<double> {
     using T = double;
-    double half_p;  // RN(p/2)
-    int sq;         // s: C = (Z^a')^(2^s)
+    double hp128;  // 128 RN(p/2)
+    int sq;        // s: C = (Z^a')^(2^s)
     __device__ double leaf(double a, double b) const
     {
-        return lp_core(__builtin_fabs(a), __builtin_fabs(b), half_p, sq, lp_binom_lds());
+        return lp_core<true>(a, b, hp128, sq);
     }
-    __device__ double node(double a, double b) const { return lp_core(a, b, half_p, sq, lp_binom_lds()); }
+    __device__ double node(double a, double b) const { return lp_core<false>(a, b, hp128, sq); }
     __device__ double finish(double r) const { return r; }
 };
 
 template <>
 struct LpEval<float> {
     using T = float;
-    double half_p;  // RN32(p/2)
+    double hp128;  // 128 RN32(p/2)
     int sq;
     __device__ float leaf(float a, float b) const
     {
-        return (float)lp_core((double)__builtin_fabsf(a), (double)__builtin_fabsf(b), half_p, sq, lp_binom_lds());
+        return (float)lp_core<true>((double)a, (double)b, hp128, sq);
     }
-    __device__ float node(float a, float b) const
-    {
-        return (float)lp_core((double)a, (double)b, half_p, sq, lp_binom_lds());
-    }
+    __device__ float node(float a, float b) const { return (float)lp_core<false>((double)a, (double)b, hp128, sq); }
     __device__ float finish(float r) const { return r; }
 };
 
 // The p node as the kernels receive it: the evaluation part, the binomial coefficients
 // and the device table of R_j and rho_j (small kernel arguments: a large argument block
-// costs several microseconds of host time per launch).  Its own evaluation (inlined into
-// the kernel body) takes the coefficients from the kernel arguments, which stay in
-// scalar registers.
+// costs several microseconds of host time per launch), which the kernel prologue copies
+// to LDS.
 template <typename T>
 struct LpNode : LpEval<T> {
-    double b[8];       // binomial coefficients b_1 .. b_7 of a' (b[7] = 0)
-    const double *rr;  // device: R_0 .. R_127, then rho_0 .. rho_127
-    __device__ T leaf(T a, T b_) const
-    {
-        return (T)lp_core((double)__builtin_fabs((double)a), (double)__builtin_fabs((double)b_), this->half_p,
-                          this->sq, b);
-    }
-    __device__ T node(T a, T b_) const { return (T)lp_core((double)a, (double)b_, this->half_p, this->sq, b); }
-    __device__ T finish(T r) const { return r; }
+    double b[LP_B_N];  // binomial coefficients b_1 .. b_5 of a' (the rest 0)
+    const double *rr;  // device: R_0 .. R_511, then rho_0 .. rho_511
 };
 
 template <typename T>
 __host__ __device__ inline LpEval<T> node_eval(const LpNode<T> &nd)
 {
-    return LpEval<T>{nd.half_p, nd.sq};
+    return LpEval<T>{nd.hp128, nd.sq};
 }
 
 // Kernel-entry hook of the nodes: the p node fills its tables (the other nodes have
@@ -236,7 +243,7 @@ __device__ __forceinline__ void node_prologue(const LpNode<T> &nd)
 // release_lp_tables (host side).
 struct LpEntry {
     int sq;
-    double b[8];
+    double b[LP_B_N];
     double *rr;  // device table
 };
 
@@ -278,16 +285,15 @@ inline int lp_node(double half_p, double a, LpNode<T> *out)
             ++en.sq;
         }
         long double bk = 1.0L;
-        for (int i = 1; i <= 7; ++i) {
+        for (int i = 1; i <= LP_B_N; ++i) {
             bk = bk * ((long double)ap - (i - 1)) / i;
-            en.b[i - 1] = (double)bk;
+            en.b[i - 1] = i <= LP_POW_TERMS ? (double)bk : 0.0;
         }
-        en.b[7] = 0.0;
-        double h[2 * LP_TAB_N];
-        for (int j = 0; j < LP_TAB_N; ++j) {
-            const long double r = std::pow(1.0L / (long double)lp_ptab_host[j], (long double)ap);
+        static double h[2 * LP_POW_N];  // under the cache lock
+        for (int j = 0; j < LP_POW_N; ++j) {
+            const long double r = std::pow(1.0L / (long double)lp_pow_host[j], (long double)ap);
             h[j] = (double)r;
-            h[LP_TAB_N + j] = (double)(r - 1.0L);
+            h[LP_POW_N + j] = j == 0 ? LP_RHO0 : (double)(r - 1.0L);  // R_0 = 1
         }
         e = hipMalloc(reinterpret_cast<void **>(&en.rr), sizeof(h));
         if (e != hipSuccess) return (int)e;
@@ -298,7 +304,7 @@ inline int lp_node(double half_p, double a, LpNode<T> *out)
         }
         it = c.map.emplace(key, en).first;
     }
-    out->half_p = half_p;
+    out->hp128 = half_p * 128.0;
     out->sq = it->second.sq;
     memcpy(out->b, it->second.b, sizeof(out->b));
     out->rr = it->second.rr;

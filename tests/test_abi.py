@@ -47,15 +47,15 @@ def test_bench_refuses_several_gpus():
 
 
 def test_p_domain_is_checked_before_any_device_work():
-    """p <= 0, NaN, or so small that RN(1/p) overflows the working precision is an
-    invalid argument (the node of Sect. 4 is built from RN(1/p)); these calls return
-    before touching the device, so a machine without a GPU can run them."""
+    """p <= 0, NaN, or so small that RN(1/p) exceeds 2^1000 (binary64) or overflows
+    (binary32) is an invalid argument (the node of Sect. 4 is built from RN(1/p)); these
+    calls return before touching the device, so a machine without a GPU can run them."""
     import ctypes
 
     vnp = pytest.importorskip("paper_2509_06220_amd")
     L = vnp.lib()
     fake = ctypes.c_void_p(256)  # never dereferenced: the argument check fails first
-    for p in (0.0, -1.0, math.nan, 1e-310, 2.0 ** -1025):
+    for p in (0.0, -1.0, math.nan, 1e-310, 2.0 ** -1025, 2.0 ** -1001):
         assert L.vnp_dnrmp(1, fake, 1, p, fake, None) == -4, p
         assert L.vnp_dnrmp_batched(1, fake, 1, fake, p, fake, None) == -5, p
         assert L.vnp_dnrmp_mat(1, 1, fake, 1, p, fake, None) == -5, p
