@@ -475,7 +475,11 @@ static int cus()
     return g_cus;
 }
 
-static BatchShape default_batch_shape() { return BatchShape{2, 8, cus() * 2}; }
+// One tile per work item: without a longest-first order (the direct calls know no host
+// lengths) the round-robin items balance best at the finest grain; measured on the 8192
+// log-uniform FP64 segments: 0.92 -> 0.83 ms for p = 2 and 2.00 -> 1.66 ms for p = 3 against
+// four tiles per item.
+static BatchShape default_batch_shape() { return BatchShape{0, 8, cus() * 2}; }
 
 static size_t coarse_bytes(int64_t nseg)
 {
