@@ -63,6 +63,7 @@ extern "C" {
 #define VNP_ENOTFOUND 100001 /* unknown ticket */
 #define VNP_EPENDING 100002 /* ticket not complete yet */
 #define VNP_ECANCELED 100003 /* request dropped unlaunched by vnp_server_destroy */
+#define VNP_ENOMEM 100004 /* request larger than the server's whole pool; host allocation failed */
 
 /* ------------------------------------------------------------------------------------
  * Single vector.  Paper: xNRMF (Sect. 1; the recommended algorithm of Sect. 3) and

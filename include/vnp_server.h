@@ -2,14 +2,18 @@
  * vnp request server: continuous batching of norm requests on one GPU.
  *
  * Serves the single-vector calls of vnp.h (xNRMF / xNRMP of Novakovic, arXiv 2509.06220,
- * Sect. 1, 3, 4) to many concurrent clients.  Request payloads live in device memory,
- * normally in the server's pool (vnp_server_alloc: admission by device memory, with
- * VNP_EAGAIN as back-pressure when the pool is full).  A batcher thread collects the
- * requests submitted so far and launches them as one batched launch per (dtype, p)
- * class on one of `streams` HIP streams; requests that arrive while batches are running
- * start in the next batch on a free stream, so their work overlaps on the device.
- * Each result is bitwise equal to the single-vector call on the same data (same
- * canonical tree), alone or in any mix.
+ * Sect. 1, 3, 4) to many concurrent clients.  Admission by device memory, two ways:
+ *   - vnp_server_submit_copy: the server copies the payload into a block of its pool when
+ *     it admits the request (in arrival order) and frees the block when the request
+ *     completes; while the pool cannot hold the next request, it and every later one wait
+ *     (back-pressure, counted in the statistics);
+ *   - vnp_server_alloc + vnp_server_submit: the caller writes the payload into a pool
+ *     block it holds (VNP_EAGAIN when the pool is full) or names any device memory.
+ * A batcher thread collects the admitted requests and launches them as one batched launch
+ * per (dtype, p) class on one of `streams` HIP streams; requests that arrive while
+ * batches are running start in the next batch on a free stream, so their work overlaps
+ * on the device.  Each result is bitwise equal to the single-vector call on the same data
+ * (same canonical tree), alone or in any mix.
  *
  * Threads: the batcher and one completion thread per stream.  While idle, each polls for
  * new work for up to 200 microseconds before it blocks, so an active server keeps up to
@@ -64,6 +68,9 @@ typedef struct {
     int64_t batch_ns;        /* total time from a batch's enqueue to its completion being seen */
     int64_t batch_ns_max;    /* longest such time */
     int64_t cancelled;       /* requests completed as VNP_ECANCELED by vnp_server_destroy */
+    int64_t admission_waits; /* copy requests that found the pool full when first considered */
+    int64_t admission_wait_ns;     /* their total wait for pool memory */
+    int64_t admission_wait_ns_max; /* the longest such wait */
 } vnp_server_stats;
 
 /* Errors: srv == NULL -> -1; cfg invalid -> -2; > 0 HIP error (pool allocation). */
@@ -86,6 +93,14 @@ int vnp_server_free(vnp_server *srv, void *dptr);
  * dtype -> -1).  The payload must stay valid until the request completes.  Errors of the
  * call: srv NULL -> -1; req NULL -> -2; ticket NULL -> -3. */
 int vnp_server_submit(vnp_server *srv, const vnp_request *req, uint64_t *ticket);
+/* As vnp_server_submit, but req->x is the caller's copy of the payload (device memory or
+ * host-mapped pinned memory, n elements with stride incx), which the server copies into a
+ * pool block of n elements when it admits the request; the norm is computed on that block
+ * (the same bits as on req->x).  req->x must stay valid until the request completes.
+ * Requests wait in arrival order while the pool cannot hold the next one; a request larger
+ * than the whole pool completes at once with status VNP_ENOMEM.  Errors as
+ * vnp_server_submit. */
+int vnp_server_submit_copy(vnp_server *srv, const vnp_request *req, uint64_t *ticket);
 /* Non-blocking: 0 and *out filled (and the ticket released) if done, else VNP_EPENDING;
  * VNP_ENOTFOUND for an unknown or already released ticket. */
 int vnp_server_poll(vnp_server *srv, uint64_t ticket, vnp_result *out);

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libvnp.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "vnp.h")
 
 F64, F32 = 0, 1
-EAGAIN, ENOTFOUND, EPENDING, ECANCELED = 100000, 100001, 100002, 100003
+EAGAIN, ENOTFOUND, EPENDING, ECANCELED, ENOMEM = 100000, 100001, 100002, 100003, 100004
 
 
 class VnpError(RuntimeError):
@@ -72,6 +72,7 @@ def lib():
             "vnp_server_alloc": [vp, i64, vp],
             "vnp_server_free": [vp, vp],
             "vnp_server_submit": [vp, vp, vp],
+            "vnp_server_submit_copy": [vp, vp, vp],
             "vnp_server_poll": [vp, ctypes.c_uint64, vp],
             "vnp_server_wait": [vp, ctypes.c_uint64, i64, vp],
             "vnp_server_get_stats": [vp, vp],
@@ -320,7 +321,8 @@ class ServerStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "rejected", "batches", "launches",
                                               "failed_batches", "max_batch_seen", "pool_free_bytes", "pool_bytes",
                                               "pending", "in_flight", "host_launch_ns", "batch_ns",
-                                              "batch_ns_max", "cancelled")]
+                                              "batch_ns_max", "cancelled", "admission_waits",
+                                              "admission_wait_ns", "admission_wait_ns_max")]
 
 
 class Server:
@@ -347,10 +349,13 @@ class Server:
     def free(self, ptr):
         _check("vnp_server_free", lib().vnp_server_free(self._h, ctypes.c_void_p(ptr)))
 
-    def submit(self, ptr, n, dtype=F64, p=2.0, incx=1):
+    def submit(self, ptr, n, dtype=F64, p=2.0, incx=1, copy=False):
+        """Queue a request on the payload at ptr; copy=True: the server copies the payload
+        into its pool when it admits the request (vnp_server_submit_copy)."""
         req = Request(dtype, float(p), int(n), ptr, int(incx))
         t = ctypes.c_uint64()
-        _check("vnp_server_submit", lib().vnp_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
+        fn = "vnp_server_submit_copy" if copy else "vnp_server_submit"
+        _check(fn, getattr(lib(), fn)(self._h, ctypes.byref(req), ctypes.byref(t)))
         return t.value
 
     def wait(self, ticket, timeout_us=-1):

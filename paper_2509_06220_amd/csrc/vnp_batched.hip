@@ -387,6 +387,39 @@ __global__ void __launch_bounds__(1024)
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += stride) dst[i] = src[i];
 }
 
+// Admission by copy (the server): copy c moves n_c logical elements of esz_c bytes,
+// element k at src_c + k inc_c (src_c: logical element 0, inc_c may be negative), to the
+// contiguous pool block dst_c.  tab: {src, dst, n, inc, esz} per copy, then chunk_off
+// (ncopy + 1 prefix sums of the copies' COPY_CHUNK-element chunks); one block per chunk.
+constexpr int64_t COPY_CHUNK = 4096;
+
+__global__ void __launch_bounds__(256) gather_kernel(const int64_t *tab, int64_t ncopy)
+{
+    const int64_t *chunk_off = tab + 5 * ncopy;
+    const int64_t b = blockIdx.x;
+    int64_t lo = 0, hi = ncopy - 1;  // the copy whose chunks hold b (block-uniform search)
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (chunk_off[mid] <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const int64_t *d = tab + 5 * lo;
+    const char *src = reinterpret_cast<const char *>(d[0]);
+    char *dst = reinterpret_cast<char *>(d[1]);
+    const int64_t n = d[2], inc = d[3], esz = d[4];
+    const int64_t k0 = (b - chunk_off[lo]) * COPY_CHUNK;
+    const int64_t k1 = k0 + COPY_CHUNK < n ? k0 + COPY_CHUNK : n;
+    if (esz == 8) {
+        for (int64_t k = k0 + threadIdx.x; k < k1; k += blockDim.x)
+            reinterpret_cast<uint64_t *>(dst)[k] = *reinterpret_cast<const uint64_t *>(src + k * inc * 8);
+    } else {
+        for (int64_t k = k0 + threadIdx.x; k < k1; k += blockDim.x)
+            reinterpret_cast<uint32_t *>(dst)[k] = *reinterpret_cast<const uint32_t *>(src + k * inc * 4);
+    }
+}
+
 // ---------------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------------
@@ -713,8 +746,22 @@ static int launch_class_p(const SegList &seg, const RequestClass &k, const int64
     return 0;
 }
 
+int64_t copy_chunks(int64_t n) { return (n + COPY_CHUNK - 1) / COPY_CHUNK; }
+
+int enqueue_copy_in(const void *h_src, void *d_desc, int64_t ncopy, int64_t nchunks, hipStream_t st)
+{
+    if (ncopy <= 0) return 0;
+    hipLaunchKernelGGL(stage_kernel, dim3(1), dim3(1024), 0, st, static_cast<const unsigned long long *>(h_src),
+                       static_cast<unsigned long long *>(d_desc), 6 * ncopy + 1);
+    if (nchunks > 0)
+        hipLaunchKernelGGL(gather_kernel, dim3((unsigned)nchunks), dim3(256), 0, st,
+                           static_cast<const int64_t *>(d_desc), ncopy);
+    return (int)hipGetLastError();
+}
+
 int enqueue_request_batch(const void *h_src, void *d_desc, int64_t nreq, const RequestClass *cls, int ncls,
-                          double *res_d, float *res_s, BatchWorkspace &ws, hipStream_t st)
+                          int64_t ncopy, int64_t nchunks, double *res_d, float *res_s, BatchWorkspace &ws,
+                          hipStream_t st)
 {
     if (nreq <= 0 || ncls <= 0) return 0;
     int64_t roots = 0;
@@ -722,8 +769,12 @@ int enqueue_request_batch(const void *h_src, void *d_desc, int64_t nreq, const R
     int rc = ensure_batch_ws(ws, 8 * (size_t)(roots > 0 ? roots : 1), (size_t)nreq, st);
     if (rc) return rc;
     const int64_t nwords = 3 * nreq + nreq + ncls;
+    const int64_t cwords = ncopy > 0 ? 6 * ncopy + 1 : 0;  // copy table after the item offsets
     hipLaunchKernelGGL(stage_kernel, dim3(1), dim3(1024), 0, st, static_cast<const unsigned long long *>(h_src),
-                       static_cast<unsigned long long *>(d_desc), nwords);
+                       static_cast<unsigned long long *>(d_desc), nwords + cwords);
+    if (ncopy > 0 && nchunks > 0)
+        hipLaunchKernelGGL(gather_kernel, dim3((unsigned)nchunks), dim3(256), 0, st,
+                           static_cast<const int64_t *>(d_desc) + nwords, ncopy);
     const int64_t *w = static_cast<const int64_t *>(d_desc);
     const void *const *ptrs = reinterpret_cast<const void *const *>(w);
     int64_t roots_off = 0;

@@ -341,3 +341,41 @@ def test_destroy_completes_dropped_requests():
     last = got["last"]
     assert (last.status == 0 and last.value == ok) or (last.status == vnp.ECANCELED and math.isnan(last.value))
     del buf
+
+
+def test_admission_by_copy_matches_the_plain_call_and_the_oracle():
+    """Payloads outside the pool (caller tensors, strided and reversed too) are copied into
+    pool blocks at admission; a pool smaller than one burst's payloads makes later copies
+    wait for memory (counted), and every result equals the plain call on the caller's data
+    and stays within the oracle's parity bound.  A payload larger than the whole pool
+    completes with VNP_ENOMEM; blocks are all returned at the end."""
+    pool = 4 << 20
+    srv = vnp.Server(pool_bytes=pool, max_batch=32, streams=2, max_wait_us=50)
+    rng = np.random.default_rng(41)
+    bufs, reqs, meta = [], [], []
+    for i in range(120):
+        dtype = vnp.F64 if rng.random() < 0.7 else vnp.F32
+        p = 2.0 if rng.random() < 0.7 else float(rng.choice([1.0, 3.0, 4.5]))
+        n = int(np.floor(2 ** rng.uniform(4, 18.5)))  # up to 370k elements: 3 MB FP64
+        incx = int(rng.choice([1, 1, 1, 2, -1]))
+        span = (n - 1) * abs(incx) + 1
+        t = torch.empty(span, dtype=torch.float64 if dtype == vnp.F64 else torch.float32, device="cuda")
+        fill_request(t.data_ptr(), n, dtype, incx, 21, i)
+        bufs.append(t)
+        reqs.append(vnp.Request(dtype, p, n, t.data_ptr(), incx))
+        meta.append((t.data_ptr(), n, dtype, p, incx))
+    big = torch.zeros(pool // 8 + 100, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    arr = (vnp.Request * len(reqs))(*reqs)
+    lat, val, st, wall = vnp_gen.run_load(srv, np.zeros(len(reqs)), arr, copy=True)
+    assert np.all(st == 0), st
+    stats = srv.stats()
+    print("admission by copy:", stats, flush=True)
+    assert stats["admission_waits"] > 0 and stats["pool_free_bytes"] == pool
+    for i, (ptr, n, dtype, p, incx) in enumerate(meta):
+        assert same(val[i], plain(ptr, n, dtype, p, incx)), i
+        if i % 4 == 0:
+            check_oracle(val[i], n, dtype, p, incx, 21, i, "admitted by copy")
+    r = srv.wait(srv.submit(big.data_ptr(), big.numel(), vnp.F64, 2.0, 1, copy=True))
+    assert r.status == vnp.ENOMEM and math.isnan(r.value)
+    srv.close()

@@ -211,9 +211,10 @@ def dev_read(src, nbytes, out, blocks, stream=0):
 LOADGEN_LIB = os.path.join(_HERE, "libvnp_loadgen.so")
 
 
-def run_load(server, arrival_s, reqs):
+def run_load(server, arrival_s, reqs, copy=False):
     """Open-loop replay of requests (vnp.Request array) at arrival times arrival_s (seconds
-    from start) against a vnp.Server; returns (latency_s, values, status, wall_s)."""
+    from start) against a vnp.Server (copy: submitted for admission by copy); returns
+    (latency_s, values, status, wall_s)."""
     import paper_2509_06220_amd as vnp
 
     lg = ctypes.CDLL(LOADGEN_LIB)
@@ -228,7 +229,8 @@ def run_load(server, arrival_s, reqs):
     st = np.zeros(n, dtype=np.int32)
     wall = ctypes.c_double()
     raddr = reqs.ctypes.data if isinstance(reqs, np.ndarray) else ctypes.addressof(reqs)
-    lg.vnpg_loadgen(server.handle, fp(L.vnp_server_submit), fp(L.vnp_server_wait), fp(L.vnp_server_clock_ns), n,
+    submit = L.vnp_server_submit_copy if copy else L.vnp_server_submit
+    lg.vnpg_loadgen(server.handle, fp(submit), fp(L.vnp_server_wait), fp(L.vnp_server_clock_ns), n,
                     arr.ctypes.data, raddr, lat.ctypes.data, val.ctypes.data, st.ctypes.data,
                     ctypes.addressof(wall))
     return lat, val, st, wall.value
