@@ -203,19 +203,24 @@ def extra_modes(torch, vnp, vnp_gen):
             _, per = time_steps(lambda: vnp.nrmp(xp, p, out=resp), 5, 1, s)
             out[f"dnrmp_p{p:g}_gbs"] = round(n * 8 / (statistics.mean(per) / 1e3) / 1e9, 1)
             if p == 3.0:
-                # the generic-p node is bound by VALU issue: FP64 FLOP rate against the FP64
-                # peak, and VALU instruction rate against the issue peak
+                # C2's roofline is HBM: the method moves n * 8 bytes.  The generic-p node is
+                # bound by VALU issue in fact; the issue fraction and the FP64 FLOP rate below
+                # count this implementation's instructions (they move when the code changes),
+                # not the method's work
                 pc = pnode_counters()
                 t_s = statistics.mean(per) / 1e3
+                gbs = n * 8 / t_s / 1e9
                 fl, ipn = pc.get("flops_per_launch"), pc.get("valu_instr_per_node")
                 out["dnrmp_p3_roofline"] = {
-                    "bound": "alu", "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS,
-                    "achieved": None if fl is None else round(fl / t_s / 1e12, 2),
-                    "frac": None if fl is None else round(fl / t_s / 1e12 / FP64_PEAK_TFLOPS, 4),
-                    "flops_per_launch": fl,
+                    "bound": "hbm", "unit": "GB/s", "peak": HBM_PEAK_GBS, "achieved": round(gbs, 1),
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes": n * 8,
                     "valu_instr_per_node": None if ipn is None else round(ipn, 1),
                     "valu_issue_frac": None if ipn is None else round(ipn * (n - 1) / t_s / 1e12 / VALU_PEAK_TLANE_OPS, 4),
                     "valu_busy_pct": None if not pc else round(pc.get("valu_busy_pct", 0.0), 1)}
+                out["dnrmp_p3_fp64_flops_implementation_counted"] = {
+                    "unit": "TFLOP/s", "peak": FP64_PEAK_TFLOPS, "flops_per_launch": fl,
+                    "achieved": None if fl is None else round(fl / t_s / 1e12, 2),
+                    "frac": None if fl is None else round(fl / t_s / 1e12 / FP64_PEAK_TFLOPS, 4)}
         del xp
         torch.cuda.empty_cache()
         # norm of a 2^15 x 2^15 FP64 array stored with leading dimension 2^15 + 64 (column
@@ -280,11 +285,19 @@ def batched_mode(torch, vnp, vnp_gen, reps=20):
             "speedup": round(tl / tb, 2), "bitwise_equal_segments": same, "segments": nseg, "plan": info}
 
 
-def served_mode(torch, vnp, vnp_gen, rates, seconds, n_payloads=4096, check=64):
+SERVE_POOL_BYTES = 256 << 20
+
+
+def served_mode(torch, vnp, vnp_gen, rates, seconds, compare_seconds, n_payloads=4096, check=64):
     """Open-loop Poisson arrivals against the request server.  Requests: L=floor(2^(4+20U)),
     FP64 with probability 0.7 else FP32, p=2 with probability 0.8 else one of {1, 3, 4.5},
-    values U[-1,1) 2^e, e in [-30, 30].  Payloads are admitted once into the server's pool
-    (generated on the device) and stay resident; each request names one of them."""
+    values U[-1,1) 2^e, e in [-30, 30].  Each request names one of n_payloads client buffers
+    (device memory outside the server, generated on the device) and is admitted by copy at
+    arrival: the server copies it into a block of its SERVE_POOL_BYTES pool (far smaller than
+    the payloads), computes, and frees the block at completion; requests that find the pool
+    full wait (back-pressure, counted).  Comparator: the same schedule (its first
+    compare_seconds) through a server that runs one plain call per request, in arrival
+    order, on one stream (max_batch 1, streams 1), with the same admission."""
     import numpy as np
 
     rng = np.random.default_rng(0)
@@ -292,18 +305,22 @@ def served_mode(torch, vnp, vnp_gen, rates, seconds, n_payloads=4096, check=64):
     is_d = rng.random(n_payloads) < 0.7
     pv = np.where(rng.random(n_payloads) < 0.8, 2.0, rng.choice([1.0, 3.0, 4.5], n_payloads))
     esz = np.where(is_d, 8, 4)
-    pool = int(np.sum(((L * esz + 255) // 256) * 256)) + (64 << 20)
-    srv = vnp.Server(pool_bytes=pool, max_batch=512, streams=4, max_wait_us=20)
+    nbytes = ((L * esz + 255) // 256) * 256
+    off = np.concatenate([[0], np.cumsum(nbytes)])
+    src = torch.empty(int(off[-1]) // 4, dtype=torch.float32, device="cuda")  # the client buffers
     hs = torch.cuda.current_stream().cuda_stream
     ptrs = np.zeros(n_payloads, dtype=np.uint64)
     for i in range(n_payloads):
-        ptrs[i] = srv.alloc(int(L[i] * esz[i]))
+        ptrs[i] = src.data_ptr() + int(off[i])
         vnp_gen.dev_fill_ptr(int(ptrs[i]), int(L[i]), "f64" if is_d[i] else "f32", kind="u11exp", lo=-30, hi=30,
                              seed=0, stream=100 + i, hip_stream=hs)
     torch.cuda.synchronize()
     out = {"workload": "Poisson arrivals, L=floor(2^(4+20U)), 70% FP64/30% FP32, p=2 80% else {1,3,4.5}, "
-                       "x=U[-1,1)*2^e, e in [-30,30]",
-           "seconds_per_rate": seconds, "resident_payloads": n_payloads, "pool_bytes": pool, "rates": {}}
+                       "x=U[-1,1)*2^e, e in [-30,30]; each request admitted by copy into the server's pool",
+           "seconds_per_rate": seconds, "client_payloads": n_payloads, "client_payload_bytes": int(off[-1]),
+           "pool_bytes": SERVE_POOL_BYTES, "comparator": "one plain call per request, FIFO, one stream "
+           "(server with max_batch 1, streams 1, same admission)", "comparator_seconds": compare_seconds,
+           "rates": {}}
 
     def schedule(rate, dur, seed):
         r = np.random.default_rng(seed)
@@ -319,16 +336,34 @@ def served_mode(torch, vnp, vnp_gen, rates, seconds, n_payloads=4096, check=64):
         req["incx"] = 1
         return arr, req, pick
 
-    arr, req, _ = schedule(5000, 0.3, 99)  # warm-up: kernels loaded, workspaces allocated
-    vnp_gen.run_load(srv, arr, req)
-    for k, rate in enumerate(rates):
-        arr, req, pick = schedule(rate, seconds, k)
+    def run(srv, arr, req, pick):
         s0 = srv.stats()
-        lat, val, st, wall = vnp_gen.run_load(srv, arr, req)
+        lat, val, st, wall = vnp_gen.run_load(srv, arr, req, copy=True)
         s1 = srv.stats()
         ok = st == 0
         nb = s1["batches"] - s0["batches"]
-        # a sample re-run alone through the plain call: bitwise equal
+        return val, {
+            "requests": int(len(arr)), "completed": int(ok.sum()), "errors": int((~ok).sum()),
+            "p50_us": round(float(np.percentile(lat[ok], 50)) * 1e6, 1),
+            "p99_us": round(float(np.percentile(lat[ok], 99)) * 1e6, 1),
+            "norms_per_s": round(float(ok.sum()) / wall, 1),
+            "gbs": round(float(np.sum((L * esz)[pick][ok])) / wall / 1e9, 2),
+            "batches": int(nb), "mean_batch": round(float(len(arr)) / max(nb, 1), 2),
+            "host_launch_us_per_batch": round((s1["host_launch_ns"] - s0["host_launch_ns"]) / max(nb, 1) / 1e3, 1),
+            "batch_us_mean": round((s1["batch_ns"] - s0["batch_ns"]) / max(nb, 1) / 1e3, 1),
+            "backpressure": int(s1["admission_waits"] - s0["admission_waits"]),
+            "backpressure_wait_us_mean": round((s1["admission_wait_ns"] - s0["admission_wait_ns"]) /
+                                               max(s1["admission_waits"] - s0["admission_waits"], 1) / 1e3, 1)}
+
+    srv = vnp.Server(pool_bytes=SERVE_POOL_BYTES, max_batch=512, streams=4, max_wait_us=20)
+    cmp_srv = vnp.Server(pool_bytes=SERVE_POOL_BYTES, max_batch=1, streams=1, max_wait_us=0)
+    for sv in (srv, cmp_srv):  # warm-up: kernels loaded, workspaces allocated
+        arr, req, _ = schedule(5000, 0.3, 99)
+        vnp_gen.run_load(sv, arr, req, copy=True)
+    for k, rate in enumerate(rates):
+        arr, req, pick = schedule(rate, seconds, k)
+        val, res = run(srv, arr, req, pick)
+        # a sample re-run alone through the plain call on the client buffer: bitwise equal
         idx = np.linspace(0, len(arr) - 1, min(check, len(arr))).astype(np.int64)
         eq = 0
         for i in idx:
@@ -340,18 +375,20 @@ def served_mode(torch, vnp, vnp_gen, rates, seconds, n_payloads=4096, check=64):
             if getattr(vnp.lib(), fn)(*args) != 0:
                 continue
             eq += int(r.item() == val[i] or (math.isnan(r.item()) and math.isnan(val[i])))
-        out["rates"][str(rate)] = {
-            "requests": int(len(arr)), "completed": int(ok.sum()), "errors": int((~ok).sum()),
-            "p50_us": round(float(np.percentile(lat[ok], 50)) * 1e6, 1),
-            "p99_us": round(float(np.percentile(lat[ok], 99)) * 1e6, 1),
-            "norms_per_s": round(float(ok.sum()) / wall, 1),
-            "gbs": round(float(np.sum((L * esz)[pick][ok])) / wall / 1e9, 2),
-            "batches": int(nb), "mean_batch": round(float(len(arr)) / max(nb, 1), 2),
-            "host_launch_us_per_batch": round((s1["host_launch_ns"] - s0["host_launch_ns"]) / max(nb, 1) / 1e3, 1),
-            "batch_us_mean": round((s1["batch_ns"] - s0["batch_ns"]) / max(nb, 1) / 1e3, 1),
-            "backpressure": 0, "sample_bitwise_equal": f"{eq}/{len(idx)}"}
-        print(json.dumps({"served_rate": rate, **out["rates"][str(rate)]}), file=sys.stderr, flush=True)
+        res["sample_bitwise_equal"] = f"{eq}/{len(idx)}"
+        # the comparator on the first compare_seconds of the same schedule, and the served
+        # mode on the same prefix
+        m = int(np.searchsorted(arr, compare_seconds))
+        _, same_window = run(srv, arr[:m], req[:m], pick[:m])
+        _, serial = run(cmp_srv, arr[:m], req[:m], pick[:m])
+        res["same_window"] = {k2: same_window[k2] for k2 in ("requests", "p50_us", "p99_us", "norms_per_s")}
+        res["comparator_plain_fifo"] = {k2: serial[k2] for k2 in ("requests", "p50_us", "p99_us", "norms_per_s",
+                                                                  "backpressure")}
+        out["rates"][str(rate)] = res
+        print(json.dumps({"served_rate": rate, **res}), file=sys.stderr, flush=True)
     srv.close()
+    cmp_srv.close()
+    del src
     return out
 
 
@@ -420,6 +457,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rates", default="5000,20000,80000")
+    ap.add_argument("--compare-seconds", type=float, default=2.0,
+                    help="length of the schedule prefix run through the plain-call comparator")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy 5 times (scale of the HBM byte counters)")
     ap.add_argument("--accuracy-study", action="store_true",
@@ -560,7 +599,7 @@ def main():
     if not args.no_serve:
         try:
             rates = [int(r) for r in args.serve_rates.split(",") if r]
-            line["served"] = served_mode(torch, vnp, vnp_gen, rates, args.serve_seconds)
+            line["served"] = served_mode(torch, vnp, vnp_gen, rates, args.serve_seconds, args.compare_seconds)
         except Exception as e:  # noqa: BLE001
             line["served"] = {"error": repr(e)}
     if not args.no_cpu:

@@ -39,21 +39,22 @@ struct RequestClass {
 int request_class_items(int dtype, const int64_t *lens, int64_t n, int64_t *item_off);
 // Enqueues one request batch on st: a stage kernel copies the descriptor words from h_src
 // (device view of host-mapped memory; ptrs[nreq] | lens[nreq] | incs[nreq] | item
-// offsets, class c's n_c + 1 entries at 3 nreq + a_c + c | for ncopy > 0 the copy table
-// of enqueue_copy_in) to d_desc (device, at least 4 nreq + ncls + 6 ncopy + 1 words); a
-// gather kernel copies the admitted payloads into their pool blocks; then one batched
+// offsets, class c's n_c + 1 entries at 3 nreq + a_c + c | for ncopy > 0 the copy table:
+// {src, dst, n, inc, esz} per copy (src: logical element 0; inc in elements, may be
+// negative), then ncopy + 1 prefix sums of copy_chunks(n), nchunks in all) to d_desc
+// (device, at least 4 nreq + ncls + 6 ncopy + 1 words); a gather kernel copies the
+// admitted payloads into their pool blocks; then one batched
 // launch per class writes request i of class c to res_d[a_c + i] or res_s[a_c + i],
 // followed by a finish launch for classes with requests of several runs.  ptrs are
 // addresses of logical element 0 (moved for negative strides); lengths are >= 0.
 int enqueue_request_batch(const void *h_src, void *d_desc, int64_t nreq, const RequestClass *cls, int ncls,
                           int64_t ncopy, int64_t nchunks, double *res_d, float *res_s, BatchWorkspace &ws,
                           hipStream_t st);
-// Copies of payloads into pool blocks: the table at h_src (device view of host-mapped
-// memory) holds {src, dst, n, inc, esz} per copy (src: logical element 0; inc in elements,
-// may be negative), then ncopy + 1 prefix sums of copy_chunks(n), nchunks in all; staged to
-// d_desc (6 ncopy + 1 words) and copied by one gather launch on st.
+// Gather-kernel chunks of a copy of n elements.
 int64_t copy_chunks(int64_t n);
-int enqueue_copy_in(const void *h_src, void *d_desc, int64_t ncopy, int64_t nchunks, hipStream_t st);
+// One copy of n elements (src: logical element 0, stride inc, esz bytes each) into the
+// contiguous dst, by one gather launch on st.
+int enqueue_copy1(const void *src, void *dst, int64_t n, int64_t inc, int64_t esz, hipStream_t st);
 void release_batch_ws(BatchWorkspace &w);
 int release_svd_workspaces();
 int set_launch_shape(int wpb, int wt);

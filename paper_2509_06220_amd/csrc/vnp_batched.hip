@@ -746,16 +746,28 @@ static int launch_class_p(const SegList &seg, const RequestClass &k, const int64
     return 0;
 }
 
+// One copy, its descriptor in the kernel arguments (a batch of one request).
+__global__ void __launch_bounds__(256)
+    gather1_kernel(const char *src, char *dst, int64_t n, int64_t inc, int64_t esz)
+{
+    const int64_t k0 = (int64_t)blockIdx.x * COPY_CHUNK;
+    const int64_t k1 = k0 + COPY_CHUNK < n ? k0 + COPY_CHUNK : n;
+    if (esz == 8) {
+        for (int64_t k = k0 + threadIdx.x; k < k1; k += blockDim.x)
+            reinterpret_cast<uint64_t *>(dst)[k] = *reinterpret_cast<const uint64_t *>(src + k * inc * 8);
+    } else {
+        for (int64_t k = k0 + threadIdx.x; k < k1; k += blockDim.x)
+            reinterpret_cast<uint32_t *>(dst)[k] = *reinterpret_cast<const uint32_t *>(src + k * inc * 4);
+    }
+}
+
 int64_t copy_chunks(int64_t n) { return (n + COPY_CHUNK - 1) / COPY_CHUNK; }
 
-int enqueue_copy_in(const void *h_src, void *d_desc, int64_t ncopy, int64_t nchunks, hipStream_t st)
+int enqueue_copy1(const void *src, void *dst, int64_t n, int64_t inc, int64_t esz, hipStream_t st)
 {
-    if (ncopy <= 0) return 0;
-    hipLaunchKernelGGL(stage_kernel, dim3(1), dim3(1024), 0, st, static_cast<const unsigned long long *>(h_src),
-                       static_cast<unsigned long long *>(d_desc), 6 * ncopy + 1);
-    if (nchunks > 0)
-        hipLaunchKernelGGL(gather_kernel, dim3((unsigned)nchunks), dim3(256), 0, st,
-                           static_cast<const int64_t *>(d_desc), ncopy);
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(gather1_kernel, dim3((unsigned)copy_chunks(n)), dim3(256), 0, st,
+                       static_cast<const char *>(src), static_cast<char *>(dst), n, inc, esz);
     return (int)hipGetLastError();
 }
 

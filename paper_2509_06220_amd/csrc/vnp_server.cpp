@@ -121,14 +121,18 @@ struct HipBackend {
         int64_t ncopy = 0;
         for (const Pending &p : reqs) ncopy += p.blk ? 1 : 0;
         if (n == 1) {
-            // one request: the single-vector call itself on the slot's stream (no descriptor
-            // staging beyond a copy-in), its result written to the slot's pinned result word
+            // one request: the single-vector call itself on the slot's stream (after one gather
+            // launch for a copy), its result written to the slot's pinned result word
             int rc = 0;
             if (ncopy) {
-                int64_t *w = reinterpret_cast<int64_t *>(s.h_desc);
-                const int64_t chunks = copy_table(reqs, w, 1);
-                rc = enqueue_copy_in(s.h_desc_dev, s.d_desc, 1, chunks, s.st);
+                vnp_request &q = reqs[0].req;
+                const int64_t esz = q.dtype == VNP_F32 ? 4 : 8;
+                const char *x = static_cast<const char *>(q.x);
+                const char *x0 = q.incx >= 0 || q.n <= 0 ? x : x + (q.n - 1) * (-q.incx) * esz;
+                rc = enqueue_copy1(x0, reqs[0].blk, q.n, q.incx, esz, s.st);
                 if (rc) return rc;
+                q.x = reqs[0].blk;  // the norm reads the copy
+                q.incx = 1;
             }
             const vnp_request &q = reqs[0].req;
             if (q.dtype == VNP_F32) {

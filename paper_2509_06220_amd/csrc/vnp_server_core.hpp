@@ -181,6 +181,7 @@ struct Server {
     std::atomic<uint64_t> work_seq{0};
     std::unique_ptr<std::atomic<uint64_t>[]> flight_seq;
     uint64_t next_ticket = 1;
+    int64_t nocopy_pending = 0;  // queued requests submitted without copy
     vnp_server_stats st{};
     int64_t batch_counter = 0;
 
@@ -235,6 +236,7 @@ struct Server {
                 if (p.blk) pool.release(p.blk);
             }
             pending.clear();
+            nocopy_pending = 0;
             work_seq.fetch_add(1, std::memory_order_release);
         }
         cv_done.notify_all();
@@ -327,9 +329,15 @@ struct Server {
         std::vector<size_t> pick;
         *blocked = false;
         const size_t limit = pending.front().solo ? 1 : (size_t)cfg.max_batch;
+        // behind a blocked copy only requests that need no memory are taken: the scan stops
+        // when none is left further back (and after a bounded window)
+        int64_t nocopy_left = nocopy_pending;
+        const size_t window = 4 * (size_t)cfg.max_batch + 4096;
         for (size_t k = 0; k < pending.size() && pick.size() < limit; ++k) {
             Pending &p = pending[k];
             if (p.solo && k > 0) break;
+            if (*blocked && (nocopy_left == 0 || k >= window)) break;
+            if (!p.copy) --nocopy_left;
             if (p.copy && !p.blk) {
                 if (*blocked) continue;
                 p.blk = pool.alloc((uint64_t)std::max<int64_t>(payload_bytes(p.req), 1));
@@ -392,17 +400,13 @@ struct Server {
             }
             std::vector<Pending> batch;
             batch.reserve(pick.size());
-            std::deque<Pending> rest;
-            size_t j = 0;
-            for (size_t k = 0; k < pending.size(); ++k) {
-                if (j < pick.size() && pick[j] == k) {
-                    batch.push_back(pending[k]);
-                    ++j;
-                } else {
-                    rest.push_back(pending[k]);
-                }
+            for (size_t k : pick) batch.push_back(pending[k]);
+            if (pick.back() + 1 == pick.size()) {  // a prefix of the queue (the usual case)
+                for (size_t k = 0; k < pick.size(); ++k) pending.pop_front();
+            } else {
+                for (auto it = pick.rbegin(); it != pick.rend(); ++it) pending.erase(pending.begin() + (ptrdiff_t)*it);
             }
-            pending.swap(rest);
+            for (const Pending &p : batch) nocopy_pending -= p.copy ? 0 : 1;
             Slot<B> &s = *free_slot;
             const int64_t bno = ++batch_counter;
             st.batches += 1;
@@ -415,6 +419,7 @@ struct Server {
                     Pending p = *it;
                     p.solo = true;
                     pending.push_front(p);
+                    nocopy_pending += p.copy ? 0 : 1;
                 }
                 continue;
             }
@@ -475,6 +480,7 @@ struct Server {
                 st.rejected += 1;
             } else {
                 pending.push_back(Pending{id, req, t, false, copy, nullptr, 0});
+                nocopy_pending += copy ? 0 : 1;
                 work_seq.fetch_add(1, std::memory_order_release);
             }
             tickets.emplace(id, tk);
