@@ -33,6 +33,19 @@ struct HypNode<float> {
     __device__ float finish(float r) const { return r; }
 };
 
+// The binary32 hypotenuse for finite operands (hyp_s_fast): the streamed tiles of the
+// binary32 Frobenius norm use it, and a wave whose tile root is NaN (an infinite or NaN
+// element, or an overflow inside a tile) is evaluated again with hyp_s.
+struct HypNodeFinite32 {
+    using T = float;
+    __device__ float leaf(float a, float b) const { return hyp_s_fast(a, b); }
+    __device__ float node(float a, float b) const { return hyp_s_fast(a, b); }
+};
+template <>
+struct TileNode<HypNode<float>> {
+    using type = HypNodeFinite32;
+};
+
 template <typename T>
 struct SumNode;
 

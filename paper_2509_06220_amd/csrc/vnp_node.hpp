@@ -121,6 +121,21 @@ __device__ __forceinline__ float hyp_s(float a, float b)
 
 __device__ __forceinline__ float hyp_s_leaf(float a, float b) { return hyp_s(a, b); }
 
+// hyp_s for finite operands, without the guard (10 instructions instead of 12).  The tiny
+// addend makes the (0, 0) node exact: b != 0 gives b^2 >= 2^-298, whose last place is
+// >= 2^-350, so RN(b^2 + 2^-400) = b^2 and s is hyp_s's; b = 0 and a != 0 likewise give
+// s = a^2; a = b = 0 gives s = 2^-400, whose root 2^-200 rounds to +0.  For finite
+// operands the minimum in hyp_s always picks the rounded root, so the two nodes agree
+// bitwise (an overflow to +inf included).  An infinite operand gives NaN (s = inf: rsq
+// gives 0 and g = inf * 0), and so does a NaN operand; a subtree of these nodes therefore
+// has a NaN root unless every node in it had finite operands, and then its root is
+// hyp_s's bitwise.
+__device__ __forceinline__ float hyp_s_fast(float a, float b)
+{
+    const double A = (double)a, B = (double)b;
+    return (float)sqrt_for_f32(__builtin_fma(A, A, __builtin_fma(B, B, 0x1p-400)));
+}
+
 // |x| of a single leaf (a one-element subtree).
 __device__ __forceinline__ double leaf_abs(double v) { return __builtin_fabs(v); }
 __device__ __forceinline__ float leaf_abs(float v) { return __builtin_fabsf(v); }

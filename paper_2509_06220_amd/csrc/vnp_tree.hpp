@@ -27,6 +27,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "vnp_node.hpp"
 
 namespace vnp {
@@ -254,14 +256,26 @@ __device__ __noinline__ typename Node::T tail_tile_root(Node nd, const typename 
 
 constexpr int MAX_LWT = 12;  // a wave covers at most 2^12 tiles
 
+// A cheaper evaluation of a node inside the streamed tiles: TileNode<Node>::type gives
+// Node's values bitwise wherever it is valid and a NaN tile root wherever it is not; a
+// wave that meets such a tile is evaluated again with Node.  Nodes without one use
+// themselves.
+template <class Node>
+struct TileNode {
+    using type = Node;
+};
+
 // Root of the 2^lwt consecutive tiles starting at tile index t0 (tiles at or beyond
 // ntiles are padding and are skipped exactly): per-lane row trees (rows in groups of U),
 // then columns, then lanes, for each tile; then the tiles, by a binary-counter stack of
 // tile roots.  One group of rows is always in flight while the previous one is reduced,
-// across tile boundaries.  FAST: contiguous, naturally aligned input.
-template <class Node, int U, bool FAST>
-__device__ __forceinline__ typename Node::T wave_root(const Node &nd, const typename Node::T *x, int64_t n,
-                                                      Stride sd, int64_t t0, int64_t ntiles, int lwt, int lane)
+// across tile boundaries.  FAST: contiguous, naturally aligned input.  The streamed
+// tiles use the node tn, the tail tile and the tile roots nd; nan_tile is set when a
+// streamed tile's root is NaN.
+template <class Node, int U, bool FAST, class TN>
+__device__ __forceinline__ typename Node::T wave_root_with(const Node &nd, const TN &tn, const typename Node::T *x,
+                                                           int64_t n, Stride sd, int64_t t0, int64_t ntiles, int lwt,
+                                                           int lane, bool &nan_tile)
 {
     using T = typename Node::T;
     using VV = Vec<T>;
@@ -300,22 +314,24 @@ __device__ __forceinline__ typename Node::T wave_root(const Node &nd, const type
         for (int c = 0; c < C; ++c) {
             T w[U / 2];
 #pragma unroll
-            for (int u = 0; u < U / 2; ++u) w[u] = nd.leaf(VV::get(v[2 * u], c), VV::get(v[2 * u + 1], c));
+            for (int u = 0; u < U / 2; ++u) w[u] = tn.leaf(VV::get(v[2 * u], c), VV::get(v[2 * u + 1], c));
 #pragma unroll
             for (int s = U / 4; s >= 1; s >>= 1) {
 #pragma unroll
-                for (int u = 0; u < s; ++u) w[u] = nd.node(w[2 * u], w[2 * u + 1]);
+                for (int u = 0; u < s; ++u) w[u] = tn.node(w[2 * u], w[2 * u + 1]);
             }
-            push<Node, T, LG>(nd, rstk[c], w[0], g);
+            push<TN, T, LG>(tn, rstk[c], w[0], g);
         }
         if (g == G - 1) {
             T t;
             if constexpr (C == 2) {
-                t = nd.node(rstk[0][LG], rstk[1][LG]);
+                t = tn.node(rstk[0][LG], rstk[1][LG]);
             } else {
-                t = nd.node(nd.node(rstk[0][LG], rstk[1][LG]), nd.node(rstk[2][LG], rstk[3][LG]));
+                t = tn.node(tn.node(rstk[0][LG], rstk[1][LG]), tn.node(rstk[2][LG], rstk[3][LG]));
             }
-            push_tile(uniform(lane_tree(nd, t, lane)), q >> LG);
+            const T root = uniform(lane_tree(tn, t, lane));
+            if constexpr (!std::is_same<TN, Node>::value) nan_tile = nan_tile || root != root;
+            push_tile(root, q >> LG);
         }
     };
 
@@ -372,6 +388,30 @@ __device__ __forceinline__ typename Node::T wave_root(const Node &nd, const type
         }
     }
     return cur;
+}
+
+// wave_root_with with Node throughout (kept out of line: waves rarely need it).
+template <class Node, int U, bool FAST>
+__device__ __noinline__ typename Node::T wave_root_plain(Node nd, const typename Node::T *x, int64_t n, Stride sd,
+                                                         int64_t t0, int64_t ntiles, int lwt, int lane)
+{
+    bool unused = false;
+    return wave_root_with<Node, U, FAST>(nd, nd, x, n, sd, t0, ntiles, lwt, lane, unused);
+}
+
+template <class Node, int U, bool FAST>
+__device__ __forceinline__ typename Node::T wave_root(const Node &nd, const typename Node::T *x, int64_t n,
+                                                      Stride sd, int64_t t0, int64_t ntiles, int lwt, int lane)
+{
+    using TN = typename TileNode<Node>::type;
+    bool nan_tile = false;
+    if constexpr (std::is_same<TN, Node>::value) {
+        return wave_root_with<Node, U, FAST>(nd, nd, x, n, sd, t0, ntiles, lwt, lane, nan_tile);
+    } else {
+        const typename Node::T r = wave_root_with<Node, U, FAST>(nd, TN{}, x, n, sd, t0, ntiles, lwt, lane, nan_tile);
+        // nan_tile is wave-uniform (it follows the tile roots)
+        return nan_tile ? wave_root_plain<Node, U, FAST>(nd, x, n, sd, t0, ntiles, lwt, lane) : r;
+    }
 }
 
 // Root of tile t by a block of TILE_WAVES waves (all waves call; contains a barrier).

@@ -140,6 +140,60 @@ def test_special_values(fmt):
     assert gpu_norm(to_dev(np.array([3 * tiny, 4 * tiny], dtype=dt))) == 5 * tiny
 
 
+def _f32_cases():
+    """binary32 inputs for the streamed tiles' finite-operand node and its NaN-root fallback:
+    zero pairs and sparse vectors, the subnormal and near-overflow ranges, an overflow
+    inside one tile, and infinities and NaNs in single tiles."""
+    n = 5 * 16384 + 333
+    big = np.float32(np.finfo(np.float32).max)
+    out = []
+    x = vnp_gen.host_fill(n, dtype="f32", kind="u11", seed=21)
+    x[np.arange(n) % 10 != 3] = 0.0  # 90% zeros: many (0, 0) leaves and zero subtrees
+    out.append(("sparse", x))
+    x = np.zeros(n, dtype=np.float32)
+    x[4 * 16384 + 7] = -3.0
+    out.append(("one nonzero", x))
+    out.append(("exp[-149,-100]", vnp_gen.host_fill(n, dtype="f32", kind="exp", lo=-149, hi=-100, seed=22)))
+    out.append(("exp[-149,60]", vnp_gen.host_fill(n, dtype="f32", kind="exp", lo=-149, hi=60, seed=23)))
+    out.append(("exp[90,126]", vnp_gen.host_fill(n, dtype="f32", kind="exp", lo=90, hi=126, seed=24)))
+    x = vnp_gen.host_fill(n, dtype="f32", kind="u11", seed=25)
+    x[2 * 16384 + 100] = big
+    x[2 * 16384 + 101] = big  # the pair overflows to +inf inside tile 2
+    out.append(("overflow in a tile", x))
+    x = vnp_gen.host_fill(n, dtype="f32", kind="u11", seed=26)
+    x[3 * 16384 - 1] = big
+    x[3 * 16384] = -big  # near-overflow values in two tiles, each tile root finite
+    out.append(("big in two tiles", x))
+    for v, name in [(np.inf, "inf"), (-np.inf, "-inf"), (np.nan, "nan")]:
+        for pos in (0, 16384 + 5, n - 1):
+            x = vnp_gen.host_fill(n, dtype="f32", kind="u11", seed=27)
+            x[pos] = v
+            out.append((f"{name} at {pos}", x))
+    x = vnp_gen.host_fill(n, dtype="f32", kind="u11", seed=28)
+    x[100], x[4 * 16384 + 9] = np.inf, np.nan
+    out.append(("inf and nan", x))
+    return out
+
+
+def test_f32_streamed_tiles_match_the_guarded_node():
+    """The streamed binary32 tiles use a node without the special-value guard and fall back
+    to the guarded node for a wave whose tile root is NaN; the small-vector kernel uses the
+    guarded node throughout.  The forced launch shapes (streamed tiles) must give the
+    small-vector kernel's bits on every case, and the oracle's value within the bound."""
+    for name, x in _f32_cases():
+        d = to_dev(x)
+        vnp.set_launch_shape(0, 0)
+        ref = gpu_norm(d)  # small vector: one block per tile, guarded node
+        o = oracle.nrmf(x, "A")
+        print(f"f32 streamed vs guarded: {name}: {ref!r} (oracle {o!r})", flush=True)
+        assert_parity(ref, o, x.size, "f32", name)
+        for wpb, wt in [(1, 1), (4, 2), (1, 8), (16, 1)]:
+            vnp.set_launch_shape(wpb, wt)
+            g = gpu_norm(d)
+            assert bits(g, "f32") == bits(ref, "f32") or (math.isnan(g) and math.isnan(ref)), (name, wpb, wt, g, ref)
+        vnp.set_launch_shape(0, 0)
+
+
 @pytest.mark.parametrize("fmt,lo,hi,expect_inf", [("f64", 990, 1023, True), ("f64", 990, 1007, False),
                                                   ("f64", -1074, -1000, False), ("f32", 94, 127, True),
                                                   ("f32", -149, -104, False)])
