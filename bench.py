@@ -392,57 +392,109 @@ def served_mode(torch, vnp, vnp_gen, rates, seconds, compare_seconds, n_payloads
     return out
 
 
-def accuracy_study(torch, vnp, vnp_gen, n_log2, seeds, np_log2, gp_log2):
-    """Synthetic analogue of the paper's accuracy study (Sect. 2 tester, Table 4): relerr
-    (Eq. (relerr), multiples of eps) against the exact norm for U(0,1) (vnp_gen, seeds 0..)
-    and N(0,1) (numpy's PCG64 standard normal, seeds 0..) inputs of n = 2^n_log2 elements,
-    for the GPU path, the oracle's A, H and Z and Theorem 1's single accumulator; and for
-    p in {1/2, 2/3, 1, sqrt 2, e, pi} (binary64, U(0,1)) the GPU (n = 2^gp_log2) and the
-    oracle's A_p (n = 2^np_log2), maximum over the seeds, against two binary128 references."""
+# The synthetic accuracy study (Sect. 5's tester on stand-in inputs, Table 4): inputs by
+# (distribution, format, seed); the GPU results are taken on the GPU machine and stored, and
+# the oracle algorithms and the exact references run on any host against them.
+STUDY_PS = {"1/2": 0.5, "2/3": 2.0 / 3.0, "1": 1.0, "sqrt2": math.sqrt(2.0), "e": math.e, "pi": math.pi}
+STUDY_BINS = [0.0, 0.25, 0.5, 0.75, 1.0, 1.25, 1.5, 1.75, 2.0, 2.5, 3.0, 4.0, 8.0, math.inf]
+
+
+def study_input(vnp_gen, dist, fmt, seed, n):
+    """U(0,1): the counter-based generator (seed, stream 51); N(0,1): numpy's PCG64
+    standard normal (seed), rounded to the format."""
+    import numpy as np
+
+    if dist == "U(0,1)":
+        return vnp_gen.host_fill(n, dtype=fmt, kind="u01", seed=seed, stream=51)
+    return np.random.default_rng(seed).standard_normal(n).astype(np.float64 if fmt == "f64" else np.float32)
+
+
+def accuracy_gpu_values(torch, vnp, vnp_gen, n_log2, seeds, pn_log2, pseeds, out_path):
+    """The GPU results of the study, as exact hex strings, written to out_path."""
+    n = 1 << n_log2
+    res = {"n": n, "seeds": seeds, "frobenius": {}, "pnorm_n": 1 << pn_log2, "pnorm_seeds": pseeds, "pnorm": {}}
+    for dist in ("U(0,1)", "N(0,1)"):
+        for fmt in ("f64", "f32"):
+            vals = []
+            for sd in range(seeds):
+                x = study_input(vnp_gen, dist, fmt, sd, n)
+                vals.append(float(vnp.nrmf(torch.from_numpy(x).cuda()).item()).hex())
+                del x
+                print(f"accuracy study (GPU): {dist} {fmt} seed {sd}", file=sys.stderr, flush=True)
+            res["frobenius"][f"{dist} {fmt}"] = vals
+    for name, p in STUDY_PS.items():
+        vals = []
+        for sd in range(pseeds):
+            xd = torch.empty(1 << pn_log2, dtype=torch.float64, device="cuda")
+            vnp_gen.dev_fill(xd, kind="u01", seed=sd, stream=61)
+            vals.append(float(vnp.nrmp(xd, p).item()).hex())
+            del xd
+        res["pnorm"][name] = vals
+        print(f"accuracy study (GPU): p = {name}", file=sys.stderr, flush=True)
+    with open(out_path, "w") as f:
+        json.dump(res, f)
+    return {"written": out_path}
+
+
+def histogram(v):
+    import numpy as np
+
+    h, _ = np.histogram(np.minimum(np.asarray(v, dtype=np.float64), 1e300), bins=STUDY_BINS)
+    return [int(c) for c in h]
+
+
+def accuracy_study(vnp_gen, gpu_path, pa_log2):
+    """relerr (Eq. (relerr), multiples of eps) against the exact norm, for the GPU results in
+    gpu_path and the oracle's A, H, Z and Theorem 1's single accumulator on the same inputs;
+    for the p-norms, the GPU (at the stored n) and the oracle's A_p (on the first 2^pa_log2
+    elements) against the binary128 references (flat, and the recursion with the rounded
+    exponents RN(p/2), RN(1/p)).  Oracle arithmetic only: runs on any host."""
     import numpy as np
 
     import oracle
 
-    n = 1 << n_log2
+    with open(gpu_path) as f:
+        g = json.load(f)
+    n, seeds = g["n"], g["seeds"]
     methods = ("gpu", "A", "H", "Z", "acc")
     frob = {}
     for dist in ("U(0,1)", "N(0,1)"):
         for fmt in ("f64", "f32"):
-            npdt = np.float64 if fmt == "f64" else np.float32
+            key = f"{dist} {fmt}"
             errs = {m: [] for m in methods}
             for sd in range(seeds):
-                if dist == "U(0,1)":
-                    x = vnp_gen.host_fill(n, dtype=fmt, kind="u01", seed=sd, stream=51)
-                else:
-                    x = np.random.default_rng(sd).standard_normal(n).astype(npdt)
+                t0 = time.time()
+                x = study_input(vnp_gen, dist, fmt, sd, n)
                 ex = oracle.exact_nrm2(x)
-                vals = {"gpu": vnp.nrmf(torch.from_numpy(x).cuda()).item(), "A": oracle.nrmf(x, "A"),
+                vals = {"gpu": float.fromhex(g["frobenius"][key][sd]), "A": oracle.nrmf(x, "A"),
                         "H": oracle.nrmf(x, "H"), "Z": oracle.nrmf(x, "Z"), "acc": oracle.nrm_acc(x)}
                 for m in methods:
                     errs[m].append(oracle.relerr(vals[m], ex, fmt))
-                print(f"accuracy study: {dist} {fmt} seed {sd} done", file=sys.stderr, flush=True)
-            key = f"{dist} {fmt}"
-            frob[key] = {m: {"max": round(max(v), 4), "mean": round(sum(v) / len(v), 4)} for m, v in errs.items()}
-            print(json.dumps({"frobenius": key, **frob[key]}), file=sys.stderr, flush=True)
-    # two references: the flat binary128 p-norm, and the recursion followed in binary128
-    # with the method's rounded exponents RN(p/2), RN(1/p) (the paper's kind of reference)
-    ps = {"1/2": 0.5, "2/3": 2.0 / 3.0, "1": 1.0, "sqrt2": math.sqrt(2.0), "e": math.e, "pi": math.pi}
-    pnorm = {}
-    for name, p in ps.items():
+                del x
+                print(f"accuracy study: {key} seed {sd} ({time.time() - t0:.1f} s) " +
+                      " ".join(f"{m}={errs[m][-1]:.3f}" for m in methods), file=sys.stderr, flush=True)
+            frob[key] = {m: {"max": round(max(v), 4), "mean": round(sum(v) / len(v), 4), "hist": histogram(v)}
+                         for m, v in errs.items()}
+    pn = {}
+    pn_n, pseeds = g["pnorm_n"], g["pnorm_seeds"]
+    for name, p in STUDY_PS.items():
         e = {"gpu_flat": [], "gpu_rec": [], "A_flat": [], "A_rec": []}
-        for sd in range(seeds):
-            x = vnp_gen.host_fill(1 << gp_log2, kind="u01", seed=sd, stream=61)
-            g = vnp.nrmp(torch.from_numpy(x).cuda(), p).item()
-            e["gpu_flat"].append(oracle.relerr(g, sum(oracle.ref_pnorm(x, p)), "f64"))
-            e["gpu_rec"].append(oracle.relerr(g, sum(oracle.ref_pnorm_R(x, p)), "f64"))
-            xs = x[:1 << np_log2]
+        for sd in range(pseeds):
+            t0 = time.time()
+            x = vnp_gen.host_fill(pn_n, kind="u01", seed=sd, stream=61)
+            gv = float.fromhex(g["pnorm"][name][sd])
+            e["gpu_flat"].append(oracle.relerr(gv, sum(oracle.ref_pnorm(x, p)), "f64"))
+            e["gpu_rec"].append(oracle.relerr(gv, sum(oracle.ref_pnorm_R(x, p)), "f64"))
+            xs = np.ascontiguousarray(x[:1 << pa_log2])
+            del x
             o = oracle.nrmp(xs, p, "A")
             e["A_flat"].append(oracle.relerr(o, sum(oracle.ref_pnorm(xs, p)), "f64"))
             e["A_rec"].append(oracle.relerr(o, sum(oracle.ref_pnorm_R(xs, p)), "f64"))
-        pnorm[name] = {k: round(max(v), 4) for k, v in e.items()}
-        print(json.dumps({"p": name, **pnorm[name]}), file=sys.stderr, flush=True)
-    return {"n": n, "seeds": seeds, "frobenius": frob,
-            "pnorm": {"gpu_n": 1 << gp_log2, "oracle_n": 1 << np_log2, "max_relerr": pnorm}}
+            print(f"accuracy study: p={name} seed {sd} ({time.time() - t0:.1f} s) " +
+                  " ".join(f"{k}={v[-1]:.3f}" for k, v in e.items()), file=sys.stderr, flush=True)
+        pn[name] = {k: {"max": round(max(v), 4), "mean": round(sum(v) / len(v), 4)} for k, v in e.items()}
+    return {"n": n, "seeds": seeds, "bins_eps": [b if b != math.inf else "inf" for b in STUDY_BINS],
+            "frobenius": frob, "pnorm": {"gpu_n": pn_n, "oracle_n": 1 << pa_log2, "seeds": pseeds, "relerr": pn}}
 
 
 def main():
@@ -461,10 +513,16 @@ def main():
                     help="length of the schedule prefix run through the plain-call comparator")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device copy 5 times (scale of the HBM byte counters)")
-    ap.add_argument("--accuracy-study", action="store_true",
-                    help="only run the synthetic accuracy study (relerr of the GPU and oracle algorithms)")
-    ap.add_argument("--study-n-log2", type=int, default=26)
+    ap.add_argument("--accuracy-gpu", metavar="OUT_JSON", default=None,
+                    help="only take the GPU results of the synthetic accuracy study and write them to OUT_JSON")
+    ap.add_argument("--accuracy-study", metavar="GPU_JSON", default=None,
+                    help="only run the oracle side of the accuracy study against the GPU results in GPU_JSON "
+                         "(no GPU needed)")
+    ap.add_argument("--study-n-log2", type=int, default=29)
     ap.add_argument("--study-seeds", type=int, default=31)
+    ap.add_argument("--study-pn-log2", type=int, default=30, help="n of the GPU p-norms of the study")
+    ap.add_argument("--study-pseeds", type=int, default=8)
+    ap.add_argument("--study-pa-log2", type=int, default=22, help="n of the oracle's A_p in the study")
     ap.add_argument("--profile-op", default=None,
                     help="only run one operation K times for a profiler: dnrmf, snrmf (n=2^30), dnrmp:<p> "
                          "(n=2^28) or batched:<p> (the 8192 FP64 segments, direct batched call)")
@@ -475,10 +533,16 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    import vnp_gen
+
+    if args.accuracy_study:
+        r = accuracy_study(vnp_gen, args.accuracy_study, args.study_pa_log2)
+        print(json.dumps({"accuracy_study": r}), flush=True)
+        return
+
     import torch
 
     import paper_2509_06220_amd as vnp
-    import vnp_gen
 
     if args.copy_calibration:
         nb = 1 << 31
@@ -491,9 +555,10 @@ def main():
         print(json.dumps({"copy_calibration_bytes": nb, "launches": 5}), flush=True)
         return
 
-    if args.accuracy_study:
-        r = accuracy_study(torch, vnp, vnp_gen, args.study_n_log2, args.study_seeds, 18, 20)
-        print(json.dumps({"accuracy_study": r}), flush=True)
+    if args.accuracy_gpu:
+        r = accuracy_gpu_values(torch, vnp, vnp_gen, args.study_n_log2, args.study_seeds, args.study_pn_log2,
+                                args.study_pseeds, args.accuracy_gpu)
+        print(json.dumps(r), flush=True)
         return
 
     if args.profile_op:
