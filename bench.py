@@ -392,9 +392,10 @@ def served_mode(torch, vnp, vnp_gen, rates, seconds, compare_seconds, n_payloads
     return out
 
 
-# The synthetic accuracy study (Sect. 5's tester on stand-in inputs, Table 4): inputs by
-# (distribution, format, seed); the GPU results are taken on the GPU machine and stored, and
-# the oracle algorithms and the exact references run on any host against them.
+# The synthetic accuracy study (the tester of Sect. 2 and Fig. 1 on stand-in inputs, and
+# Sect. 5's Table 4 for p != 2): inputs by (distribution, format, seed); the GPU results
+# are taken where the GPU is and stored, and the oracle algorithms and the exact references
+# run on any host against them.
 STUDY_PS = {"1/2": 0.5, "2/3": 2.0 / 3.0, "1": 1.0, "sqrt2": math.sqrt(2.0), "e": math.e, "pi": math.pi}
 STUDY_BINS = [0.0, 0.25, 0.5, 0.75, 1.0, 1.25, 1.5, 1.75, 2.0, 2.5, 3.0, 4.0, 8.0, math.inf]
 

@@ -1,8 +1,8 @@
-"""A reduced run of the synthetic accuracy study (Sect. 5's tester on stand-in inputs):
+"""A reduced run of the synthetic accuracy study (the tester of Sect. 2 on stand-in inputs):
 relerr (Eq. (relerr), multiples of eps) of the GPU path and of the oracle's recursive
 algorithms A, H and Z against the exact norm, for U(0,1) and N(0,1) inputs of 2^22
 elements in binary64 and binary32, three seeds each.  The paper observes errors below
-3 eps for its recursive algorithms on such inputs (Sect. 5); the single accumulator of
+3 eps for its recursive algorithms on such inputs (Sect. 2, Fig. 1); the single accumulator of
 Theorem 1 is run beside them and reported, its error growing with n."""
 import pytest
 
