@@ -79,12 +79,24 @@ struct SegList {  // independent requests: len[s] elements at ptr[s] with stride
     __device__ bool ok(int64_t, int64_t) const { return true; }
 };
 
+// Runs of a segment of `tiles` tiles: 2^L tiles each, L the smallest at or above the launch's
+// lwt that leaves at most MAX_RUNS runs (so the finish reduces at most 8 chunks of run
+// roots per segment; a very long segment is spread over waves in larger runs).  Any run
+// size gives the same tree.
+constexpr int64_t MAX_RUNS = 4096;
+__host__ __device__ inline int seg_lwt(int64_t tiles, int lwt)
+{
+    while (lwt < MAX_LWT && ((tiles + ((int64_t)1 << lwt) - 1) >> lwt) > MAX_RUNS) ++lwt;
+    return lwt;
+}
+
 template <typename T>
 __device__ __forceinline__ int64_t runs_of(int64_t len, int lwt)
 {
     constexpr int64_t TE = tile_elems<T>();
     const int64_t tiles = (len + TE - 1) / TE;
-    return (tiles + ((int64_t)1 << lwt) - 1) >> lwt;
+    const int sl = seg_lwt(tiles, lwt);
+    return (tiles + ((int64_t)1 << sl) - 1) >> sl;
 }
 
 // ---------------------------------------------------------------------------------
@@ -284,16 +296,17 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(Batche
         const int64_t r = item - item_off[k];
         const int64_t len = seg.len(s), inc = seg.inc(s);
         const int64_t ntiles = (len + TE - 1) / TE;
-        const int64_t nruns = (ntiles + ((int64_t)1 << lwt) - 1) >> lwt;
+        const int sl = seg_lwt(ntiles, lwt);
+        const int64_t nruns = (ntiles + ((int64_t)1 << sl) - 1) >> sl;
         const T *xs = seg.base(x, s);
         T root;
         if constexpr (GEN) {
             if (inc == 1 && (((uintptr_t)xs) % sizeof(T)) == 0)
-                root = wave_root<Node, U, true>(nd, xs, len, real_stride(1), r << lwt, ntiles, lwt, lane);
+                root = wave_root<Node, U, true>(nd, xs, len, real_stride(1), r << sl, ntiles, sl, lane);
             else
-                root = wave_root<Node, U, false>(nd, xs, len, real_stride(inc), r << lwt, ntiles, lwt, lane);
+                root = wave_root<Node, U, false>(nd, xs, len, real_stride(inc), r << sl, ntiles, sl, lane);
         } else {
-            root = wave_root<Node, U, true>(nd, xs, len, real_stride(1), r << lwt, ntiles, lwt, lane);
+            root = wave_root<Node, U, true>(nd, xs, len, real_stride(1), r << sl, ntiles, sl, lane);
         }
         // every lane stores the same value
         if (nruns == 1)
@@ -573,7 +586,8 @@ template <typename T>
 static bool may_multi(const SegCols &c, int lwt)
 {
     constexpr int64_t TE = tile_elems<T>();
-    return (c.m + TE - 1) / TE > ((int64_t)1 << lwt);
+    const int64_t tiles = (c.m + TE - 1) / TE;
+    return tiles > ((int64_t)1 << seg_lwt(tiles, lwt));
 }
 
 // Enqueue setup, streaming and (if needed) finish kernels for one batched workload (no
@@ -678,7 +692,8 @@ static int64_t host_runs(int64_t len, int lwt)
 {
     constexpr int64_t TE = tile_elems<T>();
     const int64_t tiles = len > 0 ? (len + TE - 1) / TE : 0;
-    return (tiles + ((int64_t)1 << lwt) - 1) >> lwt;
+    const int sl = seg_lwt(tiles, lwt);
+    return (tiles + ((int64_t)1 << sl) - 1) >> sl;
 }
 
 template <typename T>

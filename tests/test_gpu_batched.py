@@ -213,10 +213,11 @@ def test_p_plan_outlives_finalize():
 
 @pytest.mark.parametrize("fmt,p", [("f64", 2.0), ("f32", 2.0), ("f64", 3.0)])
 def test_long_segment_multipass_finish(fmt, p):
-    """One segment of more than 512 runs (2^25 + 7 FP64 or 2^26 + 7 FP32 elements: 1024
-    runs of 4 tiles at the default shape) among about a hundred short ones: its run roots
-    are reduced by the finish kernel in several passes.  Bitwise equal to the plain call
-    and within the parity bound of the oracle."""
+    """One segment of more than 512 runs (2^25 + 7 FP64 or 2^26 + 7 FP32 elements: 4097
+    tiles, above the 4096 runs a segment may have, so 2049 runs of two tiles at the default
+    shape) among about a hundred short ones: its run roots are reduced by the finish kernel
+    in several passes.  Bitwise equal to the plain call and within the parity bound of the
+    oracle."""
     long_n = (1 << 25) + 7 if fmt == "f64" else (1 << 26) + 7
     L = vnp_gen.log_uniform_lengths(100, 0, 13, seed=21)
     L[40] = long_n
