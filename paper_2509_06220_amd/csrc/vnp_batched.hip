@@ -521,11 +521,12 @@ static int cus()
     return g_cus;
 }
 
-// One tile per work item: without a longest-first order (the direct calls know no host
-// lengths) the round-robin items balance best at the finest grain; measured on the 8192
-// log-uniform FP64 segments: 0.92 -> 0.83 ms for p = 2 and 2.00 -> 1.66 ms for p = 3 against
-// four tiles per item.
-static BatchShape default_batch_shape() { return BatchShape{0, 8, cus() * 2}; }
+// One tile per work item, four rounds of resident 8-wave blocks: the direct calls know no
+// host lengths (no longest-first order), and the round-robin items balance best at the
+// finest grain with several rounds.  Measured on the 8192 log-uniform FP64 segments, p = 2:
+// 0.85 ms with one round of resident blocks, 0.80 ms with four (one tile per item); four
+// tiles per item with one round: 0.92 ms.
+static BatchShape default_batch_shape() { return BatchShape{0, 8, cus() * 8}; }
 
 static size_t coarse_bytes(int64_t nseg)
 {
@@ -534,8 +535,10 @@ static size_t coarse_bytes(int64_t nseg)
 }
 
 // Blocks of wpb waves of kernel k that are resident on one compute unit at once (with
-// the largest coarse index).  Items are assigned statically, so a grid must not exceed
-// what is resident.  Cached per kernel instantiation and block size.
+// the largest coarse index).  Items are assigned to waves statically; a grid of a few
+// rounds of resident blocks lets the hardware give the later blocks to the compute units
+// that finish first, which evens out their speeds, so grids are capped at four rounds.
+// Cached per kernel instantiation and block size.
 template <typename K>
 static int resident_blocks(K k, int wpb)
 {
@@ -560,7 +563,7 @@ static int launch_streaming(const Node &nd, const Seg &seg, const typename Node:
     using T = typename Node::T;
     auto k = batched_kernel<Node, Seg, RowsInFlight<Node>::value, GEN>;
     const int fit = cus() * resident_blocks(k, wpb);
-    if (blocks > fit) blocks = fit;
+    if (blocks > 4 * fit) blocks = 4 * fit;
     hipLaunchKernelGGL(k, dim3(blocks), dim3(wpb * WAVE), coarse_bytes(nseg), st, nd, seg, x, nseg, order, item_off,
                        lwt, static_cast<T *>(roots), res);
     return blocks;
@@ -897,11 +900,11 @@ static int plan_enqueue_any(PlanImpl &P, const BatchShape &sh, hipStream_t st, B
 static int autotune(PlanImpl &P, hipStream_t st)
 {
     // work item size x block size x waves per CU (the waves that fit at once depend on
-    // the kernel's registers; timing finds the best count)
+    // the kernel's registers; counts above them make later rounds; timing finds the best)
     std::vector<BatchShape> cands;
     for (int lwt : {0, 1, 2, 3})
         for (int wpb : {4, 8})
-            for (int wpc : {8, 12, 16, 24}) cands.push_back(BatchShape{lwt, wpb, cus() * wpc / wpb});
+            for (int wpc : {8, 16, 32, 48, 64}) cands.push_back(BatchShape{lwt, wpb, cus() * wpc / wpb});
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return (int)hipErrorUnknown;
     float best = 1e30f;
