@@ -111,78 +111,82 @@ __global__ void __launch_bounds__(1024)
     batched_setup_kernel(Seg seg, int64_t nseg, const int32_t *order, int lwt, int64_t n_total, int64_t items_cap,
                          int64_t *item_off, T *res)
 {
-    __shared__ int64_t part[1024];
+    // passes of SB positions: coalesced loads (thread t takes positions t, t + 1024, ...),
+    // run counts in LDS, each thread scans a contiguous chunk of PER there (an inclusive
+    // scan within each wave by shuffles, then the wave totals in order), coalesced stores.
+    // With n_total <= VNP_MAX_N a segment has at most 2^15 runs, so counts and offsets
+    // within a pass fit 32 bits.
+    constexpr int SB = 8192, PER = SB / 1024;
+    __shared__ int32_t runs[SB];
+    __shared__ int32_t wave_total[1024 / WAVE];
     __shared__ int bad;
-    if (threadIdx.x == 0) bad = 0;
-    __syncthreads();
-    const int64_t chunk = (nseg + blockDim.x - 1) / blockDim.x;
-    const int64_t k0 = (int64_t)threadIdx.x * chunk;
-    const int64_t k1 = k0 + chunk < nseg ? k0 + chunk : nseg;
-    int64_t sum = 0;
+    const int t = threadIdx.x, lane = t & (WAVE - 1), wv = t / WAVE, nw = blockDim.x / WAVE;
+    if (t == 0) bad = 0;
     bool any_bad = false;
-    // a thread of at most 8 positions keeps their lengths for the second pass
-    const bool one_group = k1 - k0 <= 8;
-    int64_t kept[8];
-    // groups of 8 positions: all their loads are issued before any is used
-    for (int64_t kb = k0; kb < k1; kb += 8) {
-        int64_t sg[8], len[8];
-        bool ok[8];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < nseg; base += SB) {
+        int64_t sg[PER], len[PER];
+        bool ok[PER];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const int64_t k = kb + j < k1 ? kb + j : k1 - 1;
-            sg[j] = order ? order[k] : k;
+        for (int j = 0; j < PER; ++j) {
+            const int64_t k = base + t + j * 1024;
+            const int64_t kc = k < nseg ? k : nseg - 1;
+            sg[j] = order ? order[kc] : kc;
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
+        for (int j = 0; j < PER; ++j) {
             len[j] = seg.len(sg[j]);
             ok[j] = seg.ok(sg[j], n_total);
-            kept[j] = len[j];
         }
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            if (kb + j < k1) {
-                if (len[j] == 0) res[sg[j]] = T(0);
-                any_bad = any_bad || !ok[j];
-                sum += runs_of<T>(len[j], lwt);
-            }
+        for (int j = 0; j < PER; ++j) {
+            const bool in = base + t + j * 1024 < nseg;
+            if (in && len[j] == 0) res[sg[j]] = T(0);
+            any_bad = any_bad || (in && !ok[j]);
+            runs[t + j * 1024] = in ? (int32_t)runs_of<T>(len[j], lwt) : 0;
         }
+        __syncthreads();
+        int32_t c[PER], sum = 0;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            c[j] = runs[t * PER + j];
+            sum += c[j];
+        }
+        int32_t incl = sum;
+#pragma unroll
+        for (int d = 1; d < WAVE; d <<= 1) {
+            const int32_t v = __shfl_up(incl, d);
+            if (lane >= d) incl += v;
+        }
+        if (lane == WAVE - 1) wave_total[wv] = incl;
+        __syncthreads();
+        int32_t run = incl - sum, tot = 0;
+        for (int w = 0; w < nw; ++w) {
+            const int32_t wt = wave_total[w];
+            if (w < wv) run += wt;
+            tot += wt;
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {  // exclusive offsets within the pass, in place
+            runs[t * PER + j] = run;
+            run += c[j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int64_t k = base + t + j * 1024;
+            if (k < nseg) item_off[k] = carry + runs[t + j * 1024];
+        }
+        carry += tot;
+        __syncthreads();  // runs and wave_total are reused by the next pass
     }
     if (any_bad) bad = 1;
-    part[threadIdx.x] = sum;
     __syncthreads();
-    // inclusive scan of the per-thread sums (Hillis-Steele in LDS)
-    for (int d = 1; d < (int)blockDim.x; d <<= 1) {
-        const int64_t v = threadIdx.x >= (unsigned)d ? part[threadIdx.x - d] : 0;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
-    }
-    int64_t run = threadIdx.x == 0 ? 0 : part[threadIdx.x - 1];
-    for (int64_t kb = k0; kb < k1; kb += 8) {
-        int64_t len[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            if (one_group) {
-                len[j] = kept[j];
-            } else {
-                const int64_t k = kb + j < k1 ? kb + j : k1 - 1;
-                len[j] = seg.len(order ? order[k] : k);
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            if (kb + j < k1) {
-                item_off[kb + j] = run;
-                run += runs_of<T>(len[j], lwt);
-            }
-        }
-    }
-    __syncthreads();
-    if (bad || part[blockDim.x - 1] > items_cap) {
-        for (int64_t k = k0; k < k1; ++k) res[order ? order[k] : k] = T(__builtin_nan(""));
-        if (threadIdx.x == blockDim.x - 1) item_off[nseg] = 0;
-    } else if (threadIdx.x == blockDim.x - 1) {
-        item_off[nseg] = part[blockDim.x - 1];
+    if (bad || carry > items_cap) {
+        for (int64_t k = t; k < nseg; k += blockDim.x) res[order ? order[k] : k] = T(__builtin_nan(""));
+        if (t == 0) item_off[nseg] = 0;
+    } else if (t == 0) {
+        item_off[nseg] = carry;
     }
 }
 
@@ -574,7 +578,9 @@ static void launch_finish(const Node &nd, int64_t nseg, const int32_t *order, co
                           typename Node::T *res, hipStream_t st)
 {
     using T = typename Node::T;
-    const int64_t waves = std::min<int64_t>(nseg, (int64_t)cus() * 16);
+    // one wave per position up to four rounds of 16 waves per compute unit: each position
+    // is a chain of dependent loads, which other waves overlap
+    const int64_t waves = std::min<int64_t>(nseg, (int64_t)cus() * 64);
     const int wpb = waves >= 4 ? 4 : 1;
     const int blocks = (int)((waves + wpb - 1) / wpb);
     hipLaunchKernelGGL((batched_finish_kernel<Node>), dim3(blocks), dim3(wpb * WAVE), 0, st, nd, nseg, order, item_off,
