@@ -410,8 +410,8 @@ def served_mode(torch, vnp, vnp_gen, rates, seconds, compare_seconds, n_payloads
 
 # The synthetic accuracy study (the tester of Sect. 2 and Fig. 1 on stand-in inputs, and
 # Sect. 5's Table 4 for p != 2): inputs by (distribution, format, seed); the GPU results
-# are taken where the GPU is and stored, and the oracle algorithms and the exact references
-# run on any host against them.
+# are taken here and stored, and tests/accuracy_study.py runs the oracle algorithms and the
+# exact references against them on any host.
 STUDY_PS = {"1/2": 0.5, "2/3": 2.0 / 3.0, "1": 1.0, "sqrt2": math.sqrt(2.0), "e": math.e, "pi": math.pi}
 STUDY_BINS = [0.0, 0.25, 0.5, 0.75, 1.0, 1.25, 1.5, 1.75, 2.0, 2.5, 3.0, 4.0, 8.0, math.inf]
 
@@ -453,67 +453,6 @@ def accuracy_gpu_values(torch, vnp, vnp_gen, n_log2, seeds, pn_log2, pseeds, out
     return {"written": out_path}
 
 
-def histogram(v):
-    import numpy as np
-
-    h, _ = np.histogram(np.minimum(np.asarray(v, dtype=np.float64), 1e300), bins=STUDY_BINS)
-    return [int(c) for c in h]
-
-
-def accuracy_study(vnp_gen, gpu_path, pa_log2):
-    """relerr (Eq. (relerr), multiples of eps) against the exact norm, for the GPU results in
-    gpu_path and the oracle's A, H, Z and Theorem 1's single accumulator on the same inputs;
-    for the p-norms, the GPU (at the stored n) and the oracle's A_p (on the first 2^pa_log2
-    elements) against the binary128 references (flat, and the recursion with the rounded
-    exponents RN(p/2), RN(1/p)).  Oracle arithmetic only: runs on any host."""
-    import numpy as np
-
-    import oracle
-
-    with open(gpu_path) as f:
-        g = json.load(f)
-    n, seeds = g["n"], g["seeds"]
-    methods = ("gpu", "A", "H", "Z", "acc")
-    frob = {}
-    for dist in ("U(0,1)", "N(0,1)"):
-        for fmt in ("f64", "f32"):
-            key = f"{dist} {fmt}"
-            errs = {m: [] for m in methods}
-            for sd in range(seeds):
-                t0 = time.time()
-                x = study_input(vnp_gen, dist, fmt, sd, n)
-                ex = oracle.exact_nrm2(x)
-                vals = {"gpu": float.fromhex(g["frobenius"][key][sd]), "A": oracle.nrmf(x, "A"),
-                        "H": oracle.nrmf(x, "H"), "Z": oracle.nrmf(x, "Z"), "acc": oracle.nrm_acc(x)}
-                for m in methods:
-                    errs[m].append(oracle.relerr(vals[m], ex, fmt))
-                del x
-                print(f"accuracy study: {key} seed {sd} ({time.time() - t0:.1f} s) " +
-                      " ".join(f"{m}={errs[m][-1]:.3f}" for m in methods), file=sys.stderr, flush=True)
-            frob[key] = {m: {"max": round(max(v), 4), "mean": round(sum(v) / len(v), 4), "hist": histogram(v)}
-                         for m, v in errs.items()}
-    pn = {}
-    pn_n, pseeds = g["pnorm_n"], g["pnorm_seeds"]
-    for name, p in STUDY_PS.items():
-        e = {"gpu_flat": [], "gpu_rec": [], "A_flat": [], "A_rec": []}
-        for sd in range(pseeds):
-            t0 = time.time()
-            x = vnp_gen.host_fill(pn_n, kind="u01", seed=sd, stream=61)
-            gv = float.fromhex(g["pnorm"][name][sd])
-            e["gpu_flat"].append(oracle.relerr(gv, sum(oracle.ref_pnorm(x, p)), "f64"))
-            e["gpu_rec"].append(oracle.relerr(gv, sum(oracle.ref_pnorm_R(x, p)), "f64"))
-            xs = np.ascontiguousarray(x[:1 << pa_log2])
-            del x
-            o = oracle.nrmp(xs, p, "A")
-            e["A_flat"].append(oracle.relerr(o, sum(oracle.ref_pnorm(xs, p)), "f64"))
-            e["A_rec"].append(oracle.relerr(o, sum(oracle.ref_pnorm_R(xs, p)), "f64"))
-            print(f"accuracy study: p={name} seed {sd} ({time.time() - t0:.1f} s) " +
-                  " ".join(f"{k}={v[-1]:.3f}" for k, v in e.items()), file=sys.stderr, flush=True)
-        pn[name] = {k: {"max": round(max(v), 4), "mean": round(sum(v) / len(v), 4)} for k, v in e.items()}
-    return {"n": n, "seeds": seeds, "bins_eps": [b if b != math.inf else "inf" for b in STUDY_BINS],
-            "frobenius": frob, "pnorm": {"gpu_n": pn_n, "oracle_n": 1 << pa_log2, "seeds": pseeds, "relerr": pn}}
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -532,14 +471,10 @@ def main():
                     help="only run a plain 2 GiB device copy 5 times (scale of the HBM byte counters)")
     ap.add_argument("--accuracy-gpu", metavar="OUT_JSON", default=None,
                     help="only take the GPU results of the synthetic accuracy study and write them to OUT_JSON")
-    ap.add_argument("--accuracy-study", metavar="GPU_JSON", default=None,
-                    help="only run the oracle side of the accuracy study against the GPU results in GPU_JSON "
-                         "(no GPU needed)")
     ap.add_argument("--study-n-log2", type=int, default=29)
     ap.add_argument("--study-seeds", type=int, default=31)
-    ap.add_argument("--study-pn-log2", type=int, default=30, help="n of the GPU p-norms of the study")
+    ap.add_argument("--study-pn-log2", type=int, default=26, help="n of the GPU p-norms of the study")
     ap.add_argument("--study-pseeds", type=int, default=8)
-    ap.add_argument("--study-pa-log2", type=int, default=22, help="n of the oracle's A_p in the study")
     ap.add_argument("--profile-op", default=None,
                     help="only run one operation K times for a profiler: dnrmf, snrmf (n=2^30), dnrmp:<p> "
                          "(n=2^28) or batched:<p> (the 8192 FP64 segments, direct batched call)")
@@ -552,10 +487,6 @@ def main():
 
     import vnp_gen
 
-    if args.accuracy_study:
-        r = accuracy_study(vnp_gen, args.accuracy_study, args.study_pa_log2)
-        print(json.dumps({"accuracy_study": r}), flush=True)
-        return
 
     import torch
 
