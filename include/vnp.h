@@ -189,7 +189,7 @@ typedef struct {
     int64_t n_total;          /* elements in x */
     const void *x;            /* device data */
     void *res;                /* device results, nseg elements */
-    int autotune;             /* 1: time candidate shapes on `stream` during creation */
+    int autotune;             /* 0: default shape; 1: the cached choice, else time and cache; 2: time and replace */
 } vnp_plan_desc;
 
 int vnp_plan_create(vnp_plan **plan, const vnp_plan_desc *desc, void *stream);
@@ -197,6 +197,17 @@ int vnp_plan_exec(vnp_plan *plan, void *stream);
 int vnp_plan_destroy(vnp_plan *plan);
 /* Chosen launch shape: resident blocks, waves per block, tiles per work item. */
 int vnp_plan_info(const vnp_plan *plan, int *blocks, int *waves, int *tiles_per_item);
+/* The autotune cache.  With autotune = 1, vnp_plan_create takes the shape chosen before
+ * for the same device (architecture and CU count), dtype, node kind (hypot, sum, max or
+ * generic p), size class (floor log2 of nseg and of n_total), alignment of x and tree id
+ * (vnp_tree_id) if there is one, and otherwise times the candidates and records the
+ * choice; autotune = 2 always times and replaces the record.  Records live for the
+ * process and, when the environment variable VNP_AUTOTUNE_CACHE names a file, in that
+ * file as JSON: read at the first lookup, and after each new record merged with the
+ * file's current records and rewritten through a temporary file and a rename.  A shape
+ * never changes a result, so a stale record costs only time.  vnp_autotune_cache_clear
+ * drops the process's records (the file is read again at the next lookup); returns 0. */
+int vnp_autotune_cache_clear(void);
 
 /* ------------------------------------------------------------------------------------
  * Library information.

@@ -55,6 +55,7 @@ def lib():
             "vnp_plan_exec": [vp, vp],
             "vnp_plan_destroy": [vp],
             "vnp_plan_info": [vp, vp, vp, vp],
+            "vnp_autotune_cache_clear": [],
             "vnp_dnrmf_cols": [i64, i64, vp, i64, vp, vp],
             "vnp_snrmf_cols": [i64, i64, vp, i64, vp, vp],
             "vnp_dschatten": [i64, i64, vp, i64, d, vp, vp],
@@ -193,6 +194,9 @@ class _PlanDesc(ctypes.Structure):
 class Plan:
     """A batched workload captured once (autotuned shape, HIP graph) and replayed by run().
 
+    autotune: 0 default shape; 1 (or True) the cached choice for this device, dtype, node
+    kind, size class, alignment and tree id, else time the candidates and cache the choice;
+    2 time and replace the cached choice (see vnp_autotune_cache_clear in vnp.h).
     The tensors passed here must stay alive (and keep their sizes) while the plan exists;
     their contents may change between runs."""
 
@@ -212,7 +216,7 @@ class Plan:
             self._keep.append(hoff)
         desc = _PlanDesc(F64 if x.dtype == torch.float64 else F32, float(p), nseg, offsets.data_ptr(),
                          hoff.ctypes.data if hoff is not None else None, x.numel(), x.data_ptr(), out.data_ptr(),
-                         1 if autotune else 0)
+                         int(autotune))
         self._h = ctypes.c_void_p()
         _check("vnp_plan_create", lib().vnp_plan_create(ctypes.byref(self._h), ctypes.byref(desc),
                                                         _stream(x, stream)))
@@ -402,6 +406,11 @@ def set_launch_shape(waves_per_block=0, tiles_per_wave=0):
 
 def tree_id(dtype=F64):
     return lib().vnp_tree_id(dtype)
+
+
+def autotune_cache_clear():
+    """Drop the process's autotune records (a VNP_AUTOTUNE_CACHE file is read again)."""
+    _check("vnp_autotune_cache_clear", lib().vnp_autotune_cache_clear())
 
 
 def tile_elems(dtype=F64):

@@ -18,11 +18,14 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <unistd.h>
+
 #include <algorithm>
 #include <map>
 #include <mutex>
 #include <new>
 #include <numeric>
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -901,10 +904,110 @@ static int plan_enqueue_any(PlanImpl &P, const BatchShape &sh, hipStream_t st, B
                               : plan_enqueue_p<double>(P, sh, st, 0x1p53, used);
 }
 
-// Times candidate shapes (median of 3 launches each) and keeps the fastest.  Every shape
-// computes the same tree, so the choice never changes a result.
-static int autotune(PlanImpl &P, hipStream_t st)
+// ---------------------------------------------------------------------------------
+// Autotune cache: the chosen shape per (device, dtype, node kind, size class, alignment,
+// tree id), kept for the process and, when VNP_AUTOTUNE_CACHE names a file, in that file
+// as JSON (read at the first lookup; after each new choice, merged with the file's current
+// entries and written through a temporary file and a rename).  A shape never changes a
+// result, so a stale or foreign entry can only cost time.
+// ---------------------------------------------------------------------------------
+struct TuneEntry {
+    int lwt, wpb, blocks;
+    double ms;
+};
+static std::mutex g_tune_mu;
+static std::map<std::string, TuneEntry> g_tune;
+static bool g_tune_loaded = false;
+
+static const char *tune_path()
 {
+    const char *p = getenv("VNP_AUTOTUNE_CACHE");
+    return p && p[0] ? p : nullptr;
+}
+
+// Entry lines as tune_write writes them; anything else in the file is ignored, and so is
+// an entry whose shape is outside the candidates.
+static void tune_read(const char *path, std::map<std::string, TuneEntry> &out)
+{
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char line[1024], key[512];
+    while (fgets(line, sizeof line, f)) {
+        TuneEntry e{};
+        if (sscanf(line, " \"%511[^\"]\": {\"lwt\": %d, \"wpb\": %d, \"blocks\": %d, \"ms\": %lf}", key, &e.lwt,
+                   &e.wpb, &e.blocks, &e.ms) == 5 &&
+            e.lwt >= 0 && e.lwt <= 3 && (e.wpb == 4 || e.wpb == 8) && e.blocks > 0 && e.blocks <= (1 << 20))
+            out[key] = e;
+    }
+    fclose(f);
+}
+
+static void tune_write(const char *path, const std::map<std::string, TuneEntry> &m)
+{
+    const std::string tmp = std::string(path) + ".tmp." + std::to_string((long)getpid());
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    fprintf(f, "{\n  \"version\": 1,\n  \"entries\": {\n");
+    size_t i = 0;
+    for (const auto &kv : m)
+        fprintf(f, "    \"%s\": {\"lwt\": %d, \"wpb\": %d, \"blocks\": %d, \"ms\": %.4f}%s\n", kv.first.c_str(),
+                kv.second.lwt, kv.second.wpb, kv.second.blocks, kv.second.ms, ++i < m.size() ? "," : "");
+    fprintf(f, "  }\n}\n");
+    if (fclose(f) == 0 && rename(tmp.c_str(), path) == 0) return;
+    remove(tmp.c_str());
+}
+
+static std::string tune_key(const PlanImpl &P)
+{
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return std::string();
+    const bool f32 = P.dtype == VNP_F32;
+    const double p = P.p, cutoff = f32 ? 0x1p24 : 0x1p53;
+    const char *node = p == 2.0 ? "hypot" : p == 1.0 ? "sum" : (__builtin_isinf(p) || p >= cutoff) ? "max" : "p";
+    auto lg = [](int64_t v) { return v > 0 ? 63 - __builtin_clzll((unsigned long long)v) : -1; };
+    const bool aligned = ((uintptr_t)P.x % (f32 ? 4 : 8)) == 0;
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s/%dcu|%s|%s|nseg2^%d|n2^%d|%s|tree%x", prop.gcnArchName, prop.multiProcessorCount,
+             f32 ? "f32" : "f64", node, lg(P.nseg), lg(P.n_total), aligned ? "aligned" : "unaligned",
+             vnp_tree_id(P.dtype));
+    for (char *c = buf; *c; ++c)
+        if (*c == '"' || *c == '\\' || *c < ' ') *c = '_';
+    return std::string(buf);
+}
+
+static bool tune_lookup(const std::string &key, BatchShape *sh)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!g_tune_loaded) {
+        g_tune_loaded = true;
+        if (const char *path = tune_path()) tune_read(path, g_tune);
+    }
+    auto it = g_tune.find(key);
+    if (it == g_tune.end()) return false;
+    *sh = BatchShape{it->second.lwt, it->second.wpb, it->second.blocks};
+    return true;
+}
+
+static void tune_store(const std::string &key, const BatchShape &sh, double ms)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = TuneEntry{sh.lwt, sh.wpb, sh.blocks, ms};
+    if (const char *path = tune_path()) {
+        std::map<std::string, TuneEntry> merged;
+        tune_read(path, merged);  // other processes' entries
+        for (const auto &kv : g_tune) merged[kv.first] = kv.second;
+        tune_write(path, merged);
+    }
+}
+
+// Times candidate shapes (median of 3 launches each) and keeps the fastest.  Every shape
+// computes the same tree, so the choice never changes a result.  mode 1 takes a cached
+// choice when there is one; mode 2 always times and replaces it.
+static int autotune(PlanImpl &P, hipStream_t st, int mode)
+{
+    const std::string key = tune_key(P);
+    if (mode == 1 && !key.empty() && tune_lookup(key, &P.shape)) return 0;
     // work item size x block size x waves per CU (the waves that fit at once depend on
     // the kernel's registers; counts above them make later rounds; timing finds the best)
     std::vector<BatchShape> cands;
@@ -948,6 +1051,7 @@ static int autotune(PlanImpl &P, hipStream_t st)
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     P.shape = best_s;
+    if (!rc && best < 1e30f && !key.empty()) tune_store(key, best_s, best);
     return rc;
 }
 
@@ -1007,7 +1111,7 @@ int vnp_plan_create(vnp_plan **plan, const vnp_plan_desc *d, void *stream)
     const int64_t items_cap = d->nseg + (d->n_total + te - 1) / te + 1;
     if (!rc) rc = ensure_batch_ws(P->ws, esz * (size_t)items_cap, (size_t)(d->nseg > 0 ? d->nseg : 1), st);
     if (!rc) rc = P->dtype == VNP_F32 ? plan_prepare_p<float>(*P, 0x1p24f) : plan_prepare_p<double>(*P, 0x1p53);
-    if (!rc && d->autotune && d->nseg > 0) rc = autotune(*P, st);
+    if (!rc && d->autotune && d->nseg > 0) rc = autotune(*P, st, d->autotune == 2 ? 2 : 1);
     if (!rc && d->nseg > 0) {
         // capture on a private stream (the legacy default stream cannot be captured)
         hipStream_t cs = nullptr;
@@ -1056,6 +1160,14 @@ int vnp_plan_info(const vnp_plan *plan, int *blocks, int *waves, int *tiles_per_
     if (blocks) *blocks = plan->impl->shape.blocks;
     if (waves) *waves = plan->impl->shape.wpb;
     if (tiles_per_item) *tiles_per_item = 1 << plan->impl->shape.lwt;
+    return 0;
+}
+
+int vnp_autotune_cache_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+    g_tune_loaded = false;
     return 0;
 }
 

@@ -233,3 +233,50 @@ def test_long_segment_multipass_finish(fmt, p):
         seg = xh[off[s]:off[s + 1]]
         o = oracle.nrmf(seg, "A") if p == 2.0 else oracle.nrmp(seg, p)
         assert_parity(r[s], o, max(seg.size, 1), fmt, f"segment {s}")
+
+
+def test_autotune_cache_file(tmp_path, monkeypatch):
+    """The autotune record is written to the VNP_AUTOTUNE_CACHE file as JSON, read back by a
+    later plan of the same class without timing (a shape edited into the file is the shape
+    the next plan takes), replaced by autotune = 2, and never changes a result."""
+    import json
+
+    path = tmp_path / "autotune.json"
+    monkeypatch.setenv("VNP_AUTOTUNE_CACHE", str(path))
+    vnp.autotune_cache_clear()
+    try:
+        off = _segments(5, 200)
+        n = int(off[-1])
+        x = to_dev(vnp_gen.host_fill(n, dtype="f64", kind="u11exp", lo=-30, hi=30, seed=6))
+        d_off = to_dev(off)
+        p1 = vnp.Plan(x, d_off, autotune=1)
+        ref = p1.run().clone()
+        torch.cuda.synchronize()
+        doc = json.loads(path.read_text())
+        entries = doc["entries"]
+        assert len(entries) == 1
+        key, rec = next(iter(entries.items()))
+        print("autotune record:", key, rec, p1.info(), flush=True)
+        assert "f64" in key and "hypot" in key and f"tree{vnp.tree_id(vnp.F64):x}" in key
+        assert p1.info()["tiles_per_item"] == 1 << rec["lwt"] and p1.info()["waves_per_block"] == rec["wpb"]
+        # a different, valid shape edited into the file: the next plan of the class takes it
+        edited = {"lwt": 3 if rec["lwt"] != 3 else 1, "wpb": 4 if rec["wpb"] != 4 else 8, "blocks": 256, "ms": 9.0}
+        # in the writer's one-line entry form, which the reader parses
+        path.write_text('{\n  "version": 1,\n  "entries": {\n    "%s": {"lwt": %d, "wpb": %d, "blocks": %d, '
+                        '"ms": 9.0000}\n  }\n}\n' % (key, edited["lwt"], edited["wpb"], edited["blocks"]))
+        vnp.autotune_cache_clear()
+        p2 = vnp.Plan(x, d_off, autotune=1)
+        info = p2.info()
+        assert info["tiles_per_item"] == 1 << edited["lwt"] and info["waves_per_block"] == edited["wpb"], info
+        assert info["blocks"] <= edited["blocks"]
+        assert torch.equal(p2.run(), ref)
+        # autotune = 2 times again and replaces the record
+        p3 = vnp.Plan(x, d_off, autotune=2)
+        assert torch.equal(p3.run(), ref)
+        rec3 = json.loads(path.read_text())["entries"][key]
+        assert rec3["ms"] != 9.0
+        for p in (p1, p2, p3):
+            p.close()
+    finally:
+        monkeypatch.delenv("VNP_AUTOTUNE_CACHE")
+        vnp.autotune_cache_clear()
