@@ -515,25 +515,14 @@ int release_batch_workspaces()
     return 0;
 }
 
-static int g_cus = 0;
-static int cus()
-{
-    if (!g_cus) {
-        int dev = 0, v = 0;
-        g_cus = (hipGetDevice(&dev) == hipSuccess &&
-                 hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-                    ? v
-                    : 256;
-    }
-    return g_cus;
-}
+static int cus() { return device_cus(); }
 
-// One tile per work item, four rounds of resident 8-wave blocks: the direct calls know no
+// One tile per work item, eight rounds of resident 4-wave blocks: the direct calls know no
 // host lengths (no longest-first order), and the round-robin items balance best at the
-// finest grain with several rounds.  Measured on the 8192 log-uniform FP64 segments, p = 2:
-// 0.85 ms with one round of resident blocks, 0.80 ms with four (one tile per item); four
-// tiles per item with one round: 0.92 ms.
-static BatchShape default_batch_shape() { return BatchShape{0, 8, cus() * 8}; }
+// finest grain with several rounds.  Measured on the 8192 log-uniform FP64 segments, p = 2
+// (one tile per item): 0.85 ms with one round of resident blocks, 0.79-0.80 ms with four,
+// 0.787 ms with eight; four tiles per item with one round: 0.92 ms.
+static BatchShape default_batch_shape() { return BatchShape{0, 4, cus() * 32}; }
 
 static size_t coarse_bytes(int64_t nseg)
 {
@@ -542,9 +531,9 @@ static size_t coarse_bytes(int64_t nseg)
 }
 
 // Blocks of wpb waves of kernel k that are resident on one compute unit at once (with
-// the largest coarse index).  Items are assigned to waves statically; a grid of a few
+// the largest coarse index).  Items are assigned to waves statically; a grid of several
 // rounds of resident blocks lets the hardware give the later blocks to the compute units
-// that finish first, which evens out their speeds, so grids are capped at four rounds.
+// that finish first, which evens out their speeds, so grids are capped at eight rounds.
 // Cached per kernel instantiation and block size.
 template <typename K>
 static int resident_blocks(K k, int wpb)
@@ -570,7 +559,7 @@ static int launch_streaming(const Node &nd, const Seg &seg, const typename Node:
     using T = typename Node::T;
     auto k = batched_kernel<Node, Seg, RowsInFlight<Node>::value, GEN>;
     const int fit = cus() * resident_blocks(k, wpb);
-    if (blocks > 4 * fit) blocks = 4 * fit;
+    if (blocks > 8 * fit) blocks = 8 * fit;
     hipLaunchKernelGGL(k, dim3(blocks), dim3(wpb * WAVE), coarse_bytes(nseg), st, nd, seg, x, nseg, order, item_off,
                        lwt, static_cast<T *>(roots), res);
     return blocks;
@@ -1013,7 +1002,7 @@ static int autotune(PlanImpl &P, hipStream_t st, int mode)
     std::vector<BatchShape> cands;
     for (int lwt : {0, 1, 2, 3})
         for (int wpb : {4, 8})
-            for (int wpc : {8, 16, 32, 48, 64}) cands.push_back(BatchShape{lwt, wpb, cus() * wpc / wpb});
+            for (int wpc : {16, 32, 64, 96, 128}) cands.push_back(BatchShape{lwt, wpb, cus() * wpc / wpb});
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return (int)hipErrorUnknown;
     float best = 1e30f;

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "vnp_node.hpp"
 #include "vnp_tree.hpp"
 
@@ -105,6 +107,18 @@ template <typename T>
 __host__ __device__ inline bool p_ok(T p)
 {
     return p > T(0) && T(1) / p <= T(sizeof(T) == 8 ? 0x1p1000 : 0x1.fffffep127);
+}
+
+// Compute units of the current device, cached per device (256 when the query fails).
+inline int device_cus()
+{
+    static std::atomic<int> cache[64];
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (dev >= 0 && dev < 64 && (v = cache[dev].load(std::memory_order_relaxed)) > 0) return v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    if (dev >= 0 && dev < 64) cache[dev].store(v, std::memory_order_relaxed);
+    return v;
 }
 
 // Rows per load group (one group is in flight per wave while the previous one is

@@ -99,19 +99,7 @@ struct Shape {
     int wpb, lwt;  // waves per block, log2(tiles per wave)
 };
 
-static int cu_count()
-{
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0, v = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-            cus = v;
-        else
-            cus = 256;
-    }
-    return cus;
-}
+static int cu_count() { return device_cus(); }
 
 // Blocks of 8 waves, about 128 waves per compute unit in total (eight rounds of the 16
 // resident waves of the binary64 kernel), each wave streaming an aligned run of 2^lwt tiles

@@ -73,22 +73,55 @@ constexpr int STOP_FLOOR_LOG2 = 200;
 // singular values of the copy times 2^e are those of G).
 constexpr int PAR_SCALE = 0, PAR_BOUND = 1, PAR_BAD = 2, PAR_MSCALE = 3;
 
-// One block: the largest |entry| of the m x n matrix A (leading dimension lda), which sets
-// the matrix scale exponent e (max |a| = f 2^e, f in [1/2, 1)), and the non-finite flag.
+// max |A_ij| and whether A holds a non-finite value, in two steps: blocks over (row
+// chunks x column groups) write per-block partials (at most MAX_PARTS), then one block
+// reduces them into par: the power-of-two exponent e with max |A| in [2^(e-1), 2^e)
+// (0 for an all-zero or non-finite A) and the non-finite flag.  A maximum is exact in any
+// order.
+constexpr int MAX_PARTS = 1024;
+
 template <typename T>
+__global__ void __launch_bounds__(256)
+    matrix_max_kernel(const T *A, int64_t m, int64_t n, int64_t lda, double *pmax, double *pbad)
+{
+    __shared__ double smax[256];
+    __shared__ int sbad[256];
+    double mx = 0.0;
+    int bad = 0;
+    for (int64_t j = blockIdx.y; j < n; j += gridDim.y)
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (int64_t)gridDim.x * 256) {
+            const double v = __builtin_fabs((double)A[j * lda + i]);
+            bad |= !(v <= __builtin_huge_val());
+            mx = v > mx ? v : mx;
+        }
+    smax[threadIdx.x] = mx;
+    sbad[threadIdx.x] = bad;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            smax[threadIdx.x] = smax[threadIdx.x] > smax[threadIdx.x + w] ? smax[threadIdx.x] : smax[threadIdx.x + w];
+            sbad[threadIdx.x] |= sbad[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int b = blockIdx.y * gridDim.x + blockIdx.x;
+        pmax[b] = smax[0];
+        pbad[b] = sbad[0] ? 1.0 : 0.0;
+    }
+}
+
 __global__ void __launch_bounds__(PREP_THREADS)
-    matrix_scale_kernel(const T *A, int64_t m, int64_t n, int64_t lda, double *par)
+    matrix_scale_kernel(const double *pmax, const double *pbad, int nparts, double *par)
 {
     __shared__ double smax[PREP_THREADS];
     __shared__ int sbad[PREP_THREADS];
     double mx = 0.0;
     int bad = 0;
-    for (int64_t j = 0; j < n; j++)
-        for (int64_t i = threadIdx.x; i < m; i += PREP_THREADS) {
-            const double v = __builtin_fabs((double)A[j * lda + i]);
-            bad |= !(v <= __builtin_huge_val());
-            mx = v > mx ? v : mx;
-        }
+    for (int b = threadIdx.x; b < nparts; b += PREP_THREADS) {
+        mx = pmax[b] > mx ? pmax[b] : mx;
+        bad |= pbad[b] != 0.0;
+    }
     smax[threadIdx.x] = mx;
     sbad[threadIdx.x] = bad;
     __syncthreads();
@@ -230,13 +263,20 @@ int schatten(int64_t m, int64_t n, const T *A, int64_t lda, double p, T *res, vo
     if (rocblas_set_stream(w.handle, st) != rocblas_status_success) return (int)hipErrorUnknown;
     int rc = grow(&w.a, &w.a_bytes, sizeof(T) * (size_t)m * (size_t)n, st);
     if (!rc) rc = grow(&w.s, &w.s_bytes, sizeof(T) * (size_t)(5 * k), st);
-    if (!rc) rc = grow(&w.bb, &w.bb_bytes, sizeof(double) * (size_t)(2 * k + 4), st);
+    if (!rc) rc = grow(&w.bb, &w.bb_bytes, sizeof(double) * (size_t)(2 * k + 4 + 2 * MAX_PARTS), st);
     if (rc) return rc;
     T *a = static_cast<T *>(w.a), *s = static_cast<T *>(w.s);
     T *bd = s + k, *be = s + 2 * k, *tauq = s + 3 * k, *taup = s + 4 * k;  // B's diagonal, off-diagonal
     double *bb = static_cast<double *>(w.bb);
     double *par = bb + 2 * k;
-    hipLaunchKernelGGL((matrix_scale_kernel<T>), dim3(1), dim3(PREP_THREADS), 0, st, A, m, n, lda, par);
+    // row chunks of 256 x column groups, at most MAX_PARTS blocks
+    const int gx = (int)std::min<int64_t>((m + 255) / 256, 64);
+    const int gy = (int)std::min<int64_t>(n, MAX_PARTS / gx);
+    double *pmax = par + 4, *pbad = pmax + MAX_PARTS;
+    hipLaunchKernelGGL((matrix_max_kernel<T>), dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, st, A, m, n, lda, pmax,
+                       pbad);
+    hipLaunchKernelGGL(matrix_scale_kernel, dim3(1), dim3(PREP_THREADS), 0, st, (const double *)pmax,
+                       (const double *)pbad, gx * gy, par);
     const int64_t cblocks = std::min<int64_t>((m * n + 255) / 256, 4096);
     hipLaunchKernelGGL((scaled_copy_kernel<T>), dim3((unsigned)cblocks), dim3(256), 0, st, A, m, n, lda,
                        (const double *)par, a);

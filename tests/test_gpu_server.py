@@ -81,10 +81,9 @@ def same(a, b):
     return a == b or (math.isnan(a) and math.isnan(b))
 
 
-def blocker(srv, n=1 << 29):
-    """A long FP64 p = 3 request (well over a millisecond on the device) that keeps the
-    server's only stream busy while a burst queues up behind it; returns its buffer and
-    request."""
+def blocker(srv, n=1 << 30):
+    """A long FP64 p = 3 request (about 2.5 ms on the device) that keeps the server's only
+    stream busy while a burst queues up behind it; returns its buffer and request."""
     buf = torch.empty(n, dtype=torch.float64, device="cuda")
     vnp_gen.dev_fill(buf, kind="u11", seed=77)
     torch.cuda.synchronize()
