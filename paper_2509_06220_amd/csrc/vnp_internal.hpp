@@ -141,6 +141,20 @@ struct RowsInFlight<MaxNode<double>> {
     static constexpr int value = 8;
 };
 
+// Waves per compute unit the single-vector launch aims for (several rounds of resident
+// blocks; tiles per wave follow).  The binary32 hypot kernel does twice the node work per
+// 64 KiB tile and runs best with half the waves: SNRMF n = 2^30 0.651 ms with 4 tiles per
+// wave (64 waves per CU) against 0.669 ms with 2 (128 per CU), n = 636086033 0.404 against
+// 0.411 ms (interleaved runs on MI355X); the binary64 and p-node kernels measured flat.
+template <class Node>
+struct TargetWavesPerCU {
+    static constexpr int value = 128;
+};
+template <>
+struct TargetWavesPerCU<HypNode<float>> {
+    static constexpr int value = 64;
+};
+
 // Kernel-entry hook: every thread of the block calls it before the first node evaluation
 // (a node that keeps a table in LDS fills it there).  Nothing to do for these nodes.
 template <class Node>

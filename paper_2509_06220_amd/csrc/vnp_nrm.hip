@@ -101,16 +101,17 @@ struct Shape {
 
 static int cu_count() { return device_cus(); }
 
-// Blocks of 8 waves, about 128 waves per compute unit in total (eight rounds of the 16
-// resident waves of the binary64 kernel), each wave streaming an aligned run of 2^lwt tiles
+// Blocks of 8 waves, about waves_per_cu waves per compute unit in total (128 for most
+// nodes: eight rounds of the 16 resident waves of the binary64 kernel; TargetWavesPerCU),
+// each wave streaming an aligned run of 2^lwt tiles
 // (a run's root is a subtree of the canonical tree, so the shape never changes the
 // result).  With several rounds the last, partly filled one is short and the hardware
 // gives later blocks to the compute units that finish first; measured on MI355X (FP64):
 // n = 2^30 1.267 ms either way, n = 636086033 0.838 -> 0.770 ms and n = 3e8 0.423 -> 0.379 ms
 // against two rounds.
-static Shape choose_shape(int64_t ntiles)
+static Shape choose_shape(int64_t ntiles, int waves_per_cu)
 {
-    const int64_t target_waves = (int64_t)cu_count() * 128;
+    const int64_t target_waves = (int64_t)cu_count() * waves_per_cu;
     Shape s{8, 0};
     while (((int64_t)1 << s.lwt) * target_waves < ntiles && s.lwt < MAX_LWT) ++s.lwt;
     if (ntiles < (int64_t)cu_count() * 32) s.wpb = 4;
@@ -243,7 +244,7 @@ static int run_norm_map(const Node &nd, int64_t n, const typename Node::T *base,
                                roots, ntiles, res);
         return (int)hipGetLastError();
     }
-    const Shape s = choose_shape(ntiles);
+    const Shape s = choose_shape(ntiles, TargetWavesPerCU<Node>::value);
     const int64_t per_block = (int64_t)s.wpb << s.lwt;
     const int64_t nblocks = (ntiles + per_block - 1) / per_block;
     T *roots = nullptr;
