@@ -51,13 +51,14 @@ __global__ void __launch_bounds__(1024)
     }
 }
 
-// Fixed tree over the block roots of the streaming kernel (one block).
+// Fixed tree over the block roots of the streaming kernel (one block of at most 1024
+// threads; every power-of-two width evaluates the same tree).
 template <class Node>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(1024)
     nrm_finish_kernel(Node nd, typename Node::T *roots, int64_t count, typename Node::T *res)
 {
     using T = typename Node::T;
-    __shared__ T sbuf[256];
+    __shared__ T sbuf[1024];
     node_prologue(nd);
     const T root = block_finish(nd, roots, count, sbuf);
     if (threadIdx.x == 0) *res = nd.finish(root);
@@ -191,7 +192,9 @@ static void launch(const Node &nd, bool fast, dim3 grid, dim3 block, hipStream_t
         hipLaunchKernelGGL((nrm_kernel<Node, RowsInFlight<Node>::value, false>), grid, block, 0, st, nd, x, n, sd,
                            ntiles, lwt, roots, res);
     if (grid.x > 1)
-        hipLaunchKernelGGL((nrm_finish_kernel<Node>), dim3(1), dim3(256), 0, st, nd, roots, (int64_t)grid.x, res);
+        // up to 8192 roots in one pass of 8 per thread (4096 at the automatic shape for large n)
+        hipLaunchKernelGGL((nrm_finish_kernel<Node>), dim3(1), dim3(grid.x > 2048 ? 1024 : 256), 0, st, nd, roots,
+                           (int64_t)grid.x, res);
 }
 
 // The roots buffer of one call: the stream's workspace (fixed == nullptr), or the
