@@ -205,7 +205,8 @@ int vnp_plan_info(const vnp_plan *plan, int *blocks, int *waves, int *tiles_per_
  * process and, when the environment variable VNP_AUTOTUNE_CACHE names a file, in that
  * file as JSON: read at the first lookup, and after each new record merged with the
  * file's current records and rewritten through a temporary file and a rename.  A shape
- * never changes a result, so a stale record costs only time.  vnp_autotune_cache_clear
+ * never changes a result, so a stale record costs only time; a file that cannot be read
+ * or written is ignored.  vnp_autotune_cache_clear
  * drops the process's records (the file is read again at the next lookup); returns 0. */
 int vnp_autotune_cache_clear(void);
 
