@@ -146,7 +146,9 @@ __global__ void __launch_bounds__(1024)
             const bool in = base + t + j * 1024 < nseg;
             if (in && len[j] == 0) res[sg[j]] = T(0);
             any_bad = any_bad || (in && !ok[j]);
-            runs[t + j * 1024] = in ? (int32_t)runs_of<T>(len[j], lwt) : 0;
+            // a segment outside the buffer counts no runs (its length is not bounded; the
+            // launch is rejected below), so the 32-bit pass sums cannot overflow
+            runs[t + j * 1024] = in && ok[j] ? (int32_t)runs_of<T>(len[j], lwt) : 0;
         }
         __syncthreads();
         int32_t c[PER], sum = 0;
