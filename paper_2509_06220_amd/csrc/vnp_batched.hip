@@ -519,12 +519,26 @@ int release_batch_workspaces()
 
 static int cus() { return device_cus(); }
 
-// One tile per work item, eight rounds of resident 4-wave blocks: the direct calls know no
-// host lengths (no longest-first order), and the round-robin items balance best at the
-// finest grain with several rounds.  Measured on the 8192 log-uniform FP64 segments, p = 2
-// (one tile per item): 0.85 ms with one round of resident blocks, 0.79-0.80 ms with four,
-// 0.787 ms with eight; four tiles per item with one round: 0.92 ms.
-static BatchShape default_batch_shape() { return BatchShape{0, 4, cus() * 32}; }
+// One tile per work item, several rounds of resident blocks: the direct calls know no host
+// lengths (no longest-first order), and the round-robin items balance best at the finest
+// grain with several rounds.  Measured on the 8192 log-uniform FP64 segments, p = 2 (one
+// tile per item): 0.85 ms with one round of resident blocks, 0.79-0.80 ms with four,
+// 0.787 ms with eight rounds of 4-wave blocks; four tiles per item with one round: 0.92 ms.
+// The p node fills its LDS tables in every block, so it keeps four rounds of 8-wave
+// blocks: p = 3 took 1.49 ms with those and 1.76 ms with eight rounds of 4-wave blocks.
+static BatchShape default_batch_shape(bool table_node)
+{
+    return table_node ? BatchShape{0, 8, cus() * 8} : BatchShape{0, 4, cus() * 32};
+}
+
+template <class Node>
+struct TableNode {
+    static constexpr bool value = false;
+};
+template <typename T>
+struct TableNode<LpNode<T>> {
+    static constexpr bool value = true;
+};
 
 static size_t coarse_bytes(int64_t nseg)
 {
@@ -624,7 +638,7 @@ static int run_batched(const Node &nd, const Seg &seg, const typename Node::T *x
     using T = typename Node::T;
     if (nseg == 0) return 0;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const BatchShape sh = default_batch_shape();
+    const BatchShape sh = default_batch_shape(TableNode<Node>::value);
     const int64_t items_cap = nseg + (total_elems + tile_elems<T>() - 1) / tile_elems<T>() + 1;
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -656,7 +670,7 @@ static int run_mat(const Node &nd, int64_t m, int64_t ncols, const typename Node
 {
     using T = typename Node::T;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    const BatchShape sh = default_batch_shape();
+    const BatchShape sh = default_batch_shape(TableNode<Node>::value);
     const int64_t total = (ncols - 1) * lda + m;
     const int64_t items_cap = ncols + (total + tile_elems<T>() - 1) / tile_elems<T>() + 1;
     int dev = 0;
@@ -1085,7 +1099,10 @@ int vnp_plan_create(vnp_plan **plan, const vnp_plan_desc *d, void *stream)
     P->offsets = d->offsets;
     P->x = d->x;
     P->res = d->res;
-    P->shape = default_batch_shape();
+    {  // the generic-p node, as the plan's enqueue chooses it
+        const double pp = d->p, cutoff = d->dtype == VNP_F32 ? 0x1p24 : 0x1p53;
+        P->shape = default_batch_shape(!(pp == 2.0 || pp == 1.0 || __builtin_isinf(pp) || pp >= cutoff));
+    }
     const int64_t te = d->dtype == VNP_F32 ? tile_elems<float>() : tile_elems<double>();
     const size_t esz = d->dtype == VNP_F32 ? 4 : 8;
     int rc = 0;
