@@ -283,6 +283,18 @@ def batched_mode(torch, vnp, vnp_gen, reps=20):
     torch.cuda.synchronize()
     wall_b = time.perf_counter() - t0
     ev_ms = ev_a.elapsed_time(ev_b) / reps
+    # the direct call (no plan: default shape, segments in their own order), timed the same way
+    out_d = torch.empty(nseg, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        vnp.nrm_batched(x, d_off, out=out_d)
+    torch.cuda.synchronize()
+    ev_a.record(s)
+    for _ in range(reps):
+        vnp.nrm_batched(x, d_off, out=out_d)
+    ev_b.record(s)
+    torch.cuda.synchronize()
+    direct_ms = ev_a.elapsed_time(ev_b) / reps
+    same_d = int(torch.sum(out_b.view(torch.int64) == out_d.view(torch.int64)).item())
     wall_l, per_l = time_steps(loop, max(reps // 2, 2), 1, s, min_warm_s=0.3)
     torch.cuda.synchronize()
     same = int(torch.sum(out_b.view(torch.int64) == out_l.view(torch.int64)).item())
@@ -295,6 +307,9 @@ def batched_mode(torch, vnp, vnp_gen, reps=20):
             "batched_norms_per_s": round(nseg / tb, 1), "batched_ms": round(tb * 1e3, 4),
             "batched_event_ms_per_replay": round(ev_ms, 4),
             "batched_hbm_frac": round(total * 8 / (ev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "direct_call_ms": round(direct_ms, 4),
+            "direct_call_hbm_frac": round(total * 8 / (direct_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "direct_call_bitwise_equal_to_plan": same_d,
             "batched_replays_timed": reps,
             "batched_gbs": round(total * 8 / tb / 1e9, 1),
             "plain_loop_norms_per_s": round(nseg / tl, 1), "plain_loop_ms": round(tl * 1e3, 4),

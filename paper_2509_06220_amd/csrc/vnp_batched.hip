@@ -1006,7 +1006,7 @@ static void tune_store(const std::string &key, const BatchShape &sh, double ms)
     }
 }
 
-// Times candidate shapes (median of 3 launches each) and keeps the fastest.  Every shape
+// Times candidate shapes (median of 5 launches each) and keeps the fastest.  Every shape
 // computes the same tree, so the choice never changes a result.  mode 1 takes a cached
 // choice when there is one; mode 2 always times and replaces it.
 static int autotune(PlanImpl &P, hipStream_t st, int mode)
@@ -1035,8 +1035,8 @@ static int autotune(PlanImpl &P, hipStream_t st, int mode)
         for (const BatchShape &o : seen) dup = dup || (o.lwt == c.lwt && o.wpb == c.wpb && o.blocks == c.blocks);
         if (dup) continue;
         seen.push_back(c);
-        float t[3];
-        for (int r = 0; r < 3 && !rc; ++r) {
+        float t[5];
+        for (int r = 0; r < 5 && !rc; ++r) {
             (void)hipEventRecord(a, st);
             rc = plan_enqueue_any(P, c, st);
             (void)hipEventRecord(b, st);
@@ -1044,12 +1044,12 @@ static int autotune(PlanImpl &P, hipStream_t st, int mode)
             (void)hipEventElapsedTime(&t[r], a, b);
         }
         if (rc) break;
-        std::sort(t, t + 3);
+        std::sort(t, t + 5);
         if (log)
             fprintf(stderr, "vnp autotune: tiles/item %d, waves/block %d, blocks %d: %.4f ms\n", 1 << c.lwt, c.wpb,
-                    c.blocks, t[1]);
-        if (t[1] < best) {
-            best = t[1];
+                    c.blocks, t[2]);
+        if (t[2] < best) {
+            best = t[2];
             best_s = c;
         }
     }
