@@ -5,8 +5,10 @@ binary64; prints each polynomial's largest error, evaluated by Horner's rule in 
 arithmetic on a dense grid, and writes the tables and coefficients to vnp_lp_table.hpp:
 
 * log2 f for f in [1/2, 1): 2^LOG_BITS intervals, entry {c_j, l_j} with c_j = RN(1/mid_j)
-  and l_j = RN(log2(2/c_j)); then log2 f = (l_j - 1) + log2(1 + t), t = f c_j - 1, and
-  log2(1 + t) = t g(t);
+  and l_j = RN(log2(2/c_j)), except entry 0, which takes the interval's left end:
+  c_0 = 2, l_0 = 0, so that f = 1/2 gives t = 0 and log2(2 f) = 0 exactly; then
+  log2 f = (l_j - 1) + log2(1 + t), t = f c_j - 1, and log2(1 + t) = t g(t), with g fitted
+  on [-T_MAX, 2 T_MAX] (entry 0's t lies in [0, 2^-LOG_BITS));
 * 2^y in steps of 1/2^EXP_BITS: entry j is T_j = RN(2^(j / 2^EXP_BITS));
   2^(u / 2^EXP_BITS) - 1 = u H(u) for |u| <= 1/2 (H's
   coefficients are those of (2^r - 1) / r in r = u / 2^EXP_BITS, scaled exactly by powers
@@ -54,11 +56,15 @@ def worst(err, a, b, npts=4000):
 def log_table():
     rows = []
     for j in range(1 << LOG_BITS):
+        lo, hi = mp.mpf(1) / 2 + mp.mpf(j) / 2 ** (LOG_BITS + 1), mp.mpf(1) / 2 + mp.mpf(j + 1) / 2 ** (LOG_BITS + 1)
+        if j == 0:  # left end: f = 1/2 maps to t = 0 and log2(2 f) = 0 exactly
+            rows.append((2.0, 0.0))
+            assert 0 <= hi * 2 - 1 <= 2 * T_MAX
+            continue
         mid = mp.mpf(1) / 2 + (mp.mpf(j) + mp.mpf(1) / 2) / 2 ** (LOG_BITS + 1)
         c = float(1 / mid)
         rows.append((c, float(mp.log(2 / mp.mpf(c), 2))))
         # every f of the interval has |f c_j - 1| <= T_MAX
-        lo, hi = mp.mpf(1) / 2 + mp.mpf(j) / 2 ** (LOG_BITS + 1), mp.mpf(1) / 2 + mp.mpf(j + 1) / 2 ** (LOG_BITS + 1)
         assert max(abs(lo * mp.mpf(c) - 1), abs(hi * mp.mpf(c) - 1)) <= T_MAX
     return rows
 
@@ -81,10 +87,10 @@ def main():
     # log2(1 + t) = t g(t), |t| <= T_MAX
     # (log1p and expm1: a Chebyshev node at or near 0 must not cancel)
     g = [float(c) for c in cheb_fit(lambda t: mp.log1p(t) / t / mp.log(2) if t != 0 else 1 / mp.log(2), -T_MAX,
-                                    T_MAX, LOG_DEG)]
-    wg = worst(lambda t: abs(t * horner(g, t) - mp.log(1 + t, 2)), -T_MAX, T_MAX)
-    print(f"log2(1 + t) = t g(t), |t| <= 1.01 * 2^-{LOG_BITS + 1}, degree {LOG_DEG}: max absolute error "
-          f"2^{mp.nstr(mp.log(wg, 2), 4)}")
+                                    2 * T_MAX, LOG_DEG)]
+    wg = worst(lambda t: abs(t * horner(g, t) - mp.log(1 + t, 2)), -T_MAX, 2 * T_MAX)
+    print(f"log2(1 + t) = t g(t), -1.01 * 2^-{LOG_BITS + 1} <= t <= 1.01 * 2^-{LOG_BITS}, degree {LOG_DEG}: "
+          f"max absolute error 2^{mp.nstr(mp.log(wg, 2), 4)}")
     # (2^r - 1) / r on |r| <= 2^-(EXP_BITS + 1), then scaled to u = r 2^EXP_BITS
     R = mp.mpf(2) ** -(EXP_BITS + 1)
     h = [float(c) for c in cheb_fit(lambda r: mp.expm1(r * mp.log(2)) / r if r != 0 else mp.log(2), -R, R, EXP_DEG)]
@@ -105,9 +111,10 @@ def main():
         fh.write("// Tables and coefficients of the binary64 p node in vnp_nodes_p.hpp, written by lp_coeffs.py\n")
         fh.write("// (do not edit).\n")
         fh.write(f"// log2: entry j (the top {LOG_BITS} fraction bits of f in [1/2, 1)) is {{c_j, l_j}}, c_j =\n")
-        fh.write(f"// RN(1 / mid_j), mid_j = 1/2 + (j + 1/2) / {2 ** (LOG_BITS + 1)}, l_j = RN(log2(2 / c_j)); "
-                 f"log2(1 + t) = t g(t),\n// |t| <= 1.01 * 2^-{LOG_BITS + 1}, g of degree {LOG_DEG} "
-                 f"(absolute error 2^{mp.nstr(mp.log(wg, 2), 3)}).\n")
+        fh.write(f"// RN(1 / mid_j), mid_j = 1/2 + (j + 1/2) / {2 ** (LOG_BITS + 1)}, l_j = RN(log2(2 / c_j)), "
+                 f"except c_0 = 2, l_0 = 0\n// (the left end: log2(2 f) = 0 exactly at f = 1/2); "
+                 f"log2(1 + t) = t g(t), -1.01 * 2^-{LOG_BITS + 1} <= t <=\n// 1.01 * 2^-{LOG_BITS}, "
+                 f"g of degree {LOG_DEG} (absolute error 2^{mp.nstr(mp.log(wg, 2), 3)}).\n")
         fh.write(f"// 2^y: entry j is T_j = RN(2^(j / {2 ** EXP_BITS})); 2^(u / {2 ** EXP_BITS}) - 1 = u H(u), "
                  f"|u| <= 1/2, H of degree\n// {EXP_DEG} (relative error 2^{mp.nstr(mp.log(wh, 2), 3)}).\n")
         fh.write(f"// Z^a: entry j (the top {POW_BITS} fraction bits of Z in [1, 2)) is c'_j = "

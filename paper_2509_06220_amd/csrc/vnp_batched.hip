@@ -335,7 +335,7 @@ __global__ void __launch_bounds__(TILE_WAVES * WAVE)
 {
     using T = typename Node::T;
     constexpr int64_t TE = tile_elems<T>();
-    __shared__ T part[Vec<T>::N][TILE_WAVES][WAVE];
+    __shared__ typename Node::R part[Vec<T>::N][TILE_WAVES][WAVE];
     node_prologue(nd);
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);

@@ -1,7 +1,9 @@
 // Node objects evaluated by the tree kernels.  Each provides
-//   leaf(a, b):  the node on two raw elements (signs allowed),
-//   node(a, b):  the node on two non-negative partial norms,
-//   finish(r):   the map from the tree root to the result (identity for all nodes here).
+//   leaf(a, b):     the node on two raw elements (signs allowed), as the row levels' type R,
+//   row(u, v):      the node on the per-lane row levels (R; here R = T and row = node),
+//   row_root(r):    the map from a row tree's root to T (the identity here),
+//   node(a, b):     the node on two non-negative partial norms above the rows,
+//   finish(r):      the map from the tree root to the result (identity for all nodes here).
 // Paper (Novakovic, arXiv 2509.06220): Frobenius node = hypot (Sect. 1, Eq. (hr));
 // p = 1 node = |a| + |b| (Eq. (vp1)); p = infinity node = max(|a|, |b|) (Eq. (vpI)),
 // the absolute values being needed only at the lowest level (Sect. 4).
@@ -22,6 +24,9 @@ struct HypNode;
 template <>
 struct HypNode<double> {
     using T = double;
+    using R = double;
+    __device__ double row(double a, double b) const { return node(a, b); }
+    __device__ double row_root(double r) const { return r; }
     __device__ double leaf(double a, double b) const { return hyp_d_leaf(a, b); }
     __device__ double node(double a, double b) const { return hyp_d(a, b); }
     __device__ double finish(double r) const { return r; }
@@ -30,6 +35,9 @@ struct HypNode<double> {
 template <>
 struct HypNode<float> {
     using T = float;
+    using R = float;
+    __device__ float row(float a, float b) const { return node(a, b); }
+    __device__ float row_root(float r) const { return r; }
     __device__ float leaf(float a, float b) const { return hyp_s_leaf(a, b); }
     __device__ float node(float a, float b) const { return hyp_s(a, b); }
     __device__ float finish(float r) const { return r; }
@@ -40,6 +48,9 @@ struct HypNode<float> {
 // element, or an overflow inside a tile) is evaluated again with hyp_s.
 struct HypNodeFinite32 {
     using T = float;
+    using R = float;
+    __device__ float row(float a, float b) const { return node(a, b); }
+    __device__ float row_root(float r) const { return r; }
     __device__ float leaf(float a, float b) const { return hyp_s_fast(a, b); }
     __device__ float node(float a, float b) const { return hyp_s_fast(a, b); }
 };
@@ -54,6 +65,9 @@ struct SumNode;
 template <>
 struct SumNode<double> {
     using T = double;
+    using R = double;
+    __device__ double row(double a, double b) const { return node(a, b); }
+    __device__ double row_root(double r) const { return r; }
     __device__ double leaf(double a, double b) const { return __builtin_fabs(a) + __builtin_fabs(b); }
     __device__ double node(double a, double b) const { return a + b; }
     __device__ double finish(double r) const { return r; }
@@ -62,6 +76,9 @@ struct SumNode<double> {
 template <>
 struct SumNode<float> {
     using T = float;
+    using R = float;
+    __device__ float row(float a, float b) const { return node(a, b); }
+    __device__ float row_root(float r) const { return r; }
     __device__ float leaf(float a, float b) const { return __builtin_fabsf(a) + __builtin_fabsf(b); }
     __device__ float node(float a, float b) const { return a + b; }
     __device__ float finish(float r) const { return r; }
@@ -76,6 +93,9 @@ struct MaxNode;
 template <>
 struct MaxNode<double> {
     using T = double;
+    using R = double;
+    __device__ double row(double a, double b) const { return node(a, b); }
+    __device__ double row_root(double r) const { return r; }
     __device__ static double mx(double a, double b)
     {
         const uint64_t ia = (uint64_t)__double_as_longlong(a), ib = (uint64_t)__double_as_longlong(b);
@@ -89,6 +109,9 @@ struct MaxNode<double> {
 template <>
 struct MaxNode<float> {
     using T = float;
+    using R = float;
+    __device__ float row(float a, float b) const { return node(a, b); }
+    __device__ float row_root(float r) const { return r; }
     __device__ static float mx(float a, float b)
     {
         const uint32_t ia = __float_as_uint(a), ib = __float_as_uint(b);

@@ -10,8 +10,9 @@
 // general-purpose library routines and without a division, from tables in LDS:
 //   S = 2^((p/2) log2 Q),  log2 Q = (e_m - e_M) + log2 f_m - log2 f_M  (frexp parts f in
 //   [1/2, 1), exponents e).  log2 f: the top LP_LOG_BITS fraction bits of f pick c_j ~ 1/f
-//   and l_j = log2(2 / c_j); log2 f + 1 = l_j + t g(t), t = fma(f, c_j, -1), |t| <= 1.01 *
-//   2^-11, g of degree 3, evaluated as fma(t, g, l_j).
+//   and l_j = log2(2 / c_j); log2 f + 1 = l_j + t g(t), t = fma(f, c_j, -1), -1.01 * 2^-11
+//   <= t <= 1.01 * 2^-10, g of degree 3, evaluated as fma(t, g, l_j).  Entry 0 is the
+//   interval's left end (c_0 = 2, l_0 = 0), so that f = 1/2 gives exactly 0.
 //   2^(y/128) for y = 128 (p/2) log2 Q: y = 128 k + j + u with integers k, j in [0, 128)
 //   and |u| <= 1/2 (rounding y to an integer by adding 1.5 * 2^52, whose low word then
 //   holds it), 2^(y/128) = 2^k T_j (1 + u H(u)), T_j = RN(2^(j/128)), H of degree 4.
@@ -27,7 +28,7 @@
 // (Coefficients and tables: Chebyshev fits and 60-digit values written by lp_coeffs.py.)
 //
 // Errors: the log2 table values carry 2^-54 absolute and the two fma(t, g, l_j) 2^-54
-// each, g 2^-59.6 (absolute), 1 + u H(u) 2^-62.8 and T_j 2^-53 (relative); the binomial
+// each, g 2^-56.4 (absolute), 1 + u H(u) 2^-62.8 and T_j 2^-53 (relative); the binomial
 // series omits less than 2^-59.4.  An absolute error d in log2 Q changes C by at most
 // (ln 2 / 2) d relatively, whatever p is (the error of S^2 is weighted by
 // S^2 / (p (1 + S^2)) in C); each squaring doubles the relative error of Z^a', so p < 1/2
@@ -40,6 +41,9 @@
 // infinite M and equals M whenever w < 2^-54; a NaN operand turns w into a quiet NaN.
 // m = 0 (Q = 0) clears the high word of S: what is left is below 2^-1042, its square
 // vanishes, Z = 1, w = 2^(s - 1074) at most, and node(M, 0) = M exactly.
+//
+// This value form evaluates every node of binary32 and the levels above the per-lane rows of
+// binary64; the binary64 row levels carry logarithms instead (LpPair, below).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -184,20 +188,129 @@ __device__ __forceinline__ double lp_core(double a, double b, double hp128, int 
     return __builtin_fma(M, __longlong_as_double((long long)(((uint64_t)whi << 32) | (wb & 0xffffffffu))), M);
 }
 
-// The evaluation part of the p node: 128 RN(p/2) and s, with every table read from LDS.
-// Device functions that are not inlined receive this part only (node_eval).
+// ---------------------------------------------------------------------------------
+// The row levels of the binary64 p node in the logarithmic domain.
+//
+// The per-lane row tree (the lowest six levels, 63 of every 64 nodes) carries each partial
+// norm v as a pair (l, e) with v = 2^(e + l), l in [0, 1) and e an integer.  Its node is
+// Sect. 4's node(a, b) = M (1 + Q^p)^(1/p) with the logarithm taken of both sides:
+//     log2 node = log2 M + (1/p) log2(1 + 2^(p d)),  d = log2 m - log2 M = -|log2 a - log2 b|,
+// with 2^(p d) = S^2 = Q^(2 RN(p/2)) and 1/p = RN(1/p) (the exponents rounded once, Sect. 4).
+// An internal row node therefore needs no logarithm of its operands and no power: one 2^y
+// (the table above, y = 128 p d), one log2(1 + S^2) (the log2 table at (1 + S^2)/2, whose
+// rounding is that of Z = fma(S, S, 1)), and an fma; a leaf takes the logarithms of its two
+// elements first.  The row root goes back to a value, 2^l scaled by 2^e, and the levels above
+// (columns, lanes, tiles, runs, blocks) use the value node lp_core.
+//
+// Exactness and special values:
+//   * node(v, 0) = v exactly: a zero operand gives S^2 = 0, (1 + S^2)/2 = 1/2, whose log2
+//     table entry (c_0 = 2, l_0 = 0) gives log2 = 0 exactly, and l + 0 keeps l and e; the
+//     zero padding of the tree is therefore exact.
+//   * +0 is e <= -2^29 (LP_ZERO_E = -2^30), +inf e in [2^27, 2^29) (LP_INF_E), NaN e >= 2^29
+//     (LP_NAN_E), each with l = 0, set by the leaves.  The row node orders such pairs like
+//     the values they stand for (NaN above inf above every finite value above +0), and a
+//     level moves e by at most 1/p + 1, so six levels keep every class apart while
+//     1/p <= 2^20 (for larger 1/p, i.e. p below about 9.5e-7, the node stays in the value
+//     domain: the uniform flag `pair`).  The conversion to a value maps e beyond the
+//     binary64 range to +inf or +0 by ldexp, and NaN pairs to NaN.
+//   * Errors per row node: the two table functions (2^-54 each, absolute in log2), the
+//     rounding of (1 + S^2)/2, which reaches log2 multiplied by 1/p as in Sect. 4's C = Z^(1/p),
+//     and the rounding of l (2^-54 absolute); in the value these are relative errors times
+//     ln 2.
+struct LpPair {
+    double l;  // in [0, 1)
+    int e;
+};
+constexpr int LP_ZERO_E = -(1 << 30);
+constexpr int LP_INF_E = 1 << 28;
+constexpr int LP_NAN_E = 1 << 29;
+constexpr double LP_PAIR_MAX_IA = 0x1p20;  // largest 1/p of the logarithmic row levels
+
+// The common tail of the row node and the leaf: log2 M + (1/p) log2(1 + 2^y) as a pair,
+// for y = 128 p d <= 0 (y = 128 p d clamped; d <= 0 up to the table's rounding, which
+// -|d| absorbs).
+__device__ __forceinline__ LpPair lp_pair_tail(double d, double lM, int eM, double p128, double ia)
+{
+    const double y = __builtin_fmax(-p128 * __builtin_fabs(d), -2100.0 * 128);
+    const double S2 = exp2_tab(y);
+    // (1 + S^2)/2 in [1/2, 1]; 1 (m = M) is taken as its predecessor, within the rounding
+    // of the sum
+    const double Zh = __builtin_fmin(__builtin_fma(S2, 0.5, 0.5), 0x1.fffffffffffffp-1);
+    const double lr = __builtin_fma(ia, log2_p1(Zh), lM);  // >= 0
+    return LpPair{__builtin_amdgcn_fract(lr), eM + (int)lr};  // (int) truncates: floor
+}
+
+// Row node on two pairs.
+__device__ __forceinline__ LpPair lp_pair_node(LpPair a, LpPair b, double p128, double ia)
+{
+    const double d = (double)(a.e - b.e) + (a.l - b.l);  // log2 a - log2 b
+    const bool ga = d >= 0.0;
+    return lp_pair_tail(d, ga ? a.l : b.l, ga ? a.e : b.e, p128, ia);
+}
+
+// Leaf on two elements (signs allowed): log2 |a|, log2 |b| from the log2 table, then the
+// row node.
+__device__ __forceinline__ LpPair lp_pair_leaf(double a, double b, double p128, double ia)
+{
+    double M, m;
+    asm("v_max_f64 %0, |%1|, |%2|" : "=v"(M) : "v"(a), "v"(b));
+    asm("v_min_f64 %0, |%1|, |%2|" : "=v"(m) : "v"(a), "v"(b));
+    const double lM = log2_p1(__builtin_amdgcn_frexp_mant(M));
+    const double lm = log2_p1(__builtin_amdgcn_frexp_mant(m));
+    // frexp's exponents are one above those of the mantissa in [1, 2); equal offsets cancel
+    const int eM = __builtin_amdgcn_frexp_exp(M);
+    const int em = m > 0.0 ? __builtin_amdgcn_frexp_exp(m) : LP_ZERO_E;
+    LpPair r = lp_pair_tail((double)(em - eM) + (lm - lM), lM, eM - 1, p128, ia);
+    // both zero: the e of +0 (l stays finite: the table at f = 0 gives a finite value)
+    r.e = M > 0.0 ? r.e : LP_ZERO_E;
+    // an infinite or NaN operand: l = 0 (the logarithm of inf is not finite) and the class's e
+    const bool nan = __builtin_isunordered(a, b);
+    if (nan || __builtin_isinf(M)) r = LpPair{0.0, nan ? LP_NAN_E : LP_INF_E};
+    return r;
+}
+
+// The value of a pair: 2^l from the 2^y table (y = 128 l in [0, 128)), scaled by 2^e.
+__device__ __forceinline__ double lp_pair_value(LpPair v)
+{
+    const double y = v.l * 128.0;
+    const double big = y + 0x1.8p52;
+    const int k = (int)(uint32_t)(uint64_t)__double_as_longlong(big);
+    const double u = y - (big - 0x1.8p52);
+    const double T = lp_exp_lds()[k & (LP_EXP_N - 1)];
+    const double *Hc = lp_coef_lds() + LP_H_OFF;
+    double h = Hc[0];
+#pragma unroll
+    for (int i = 1; i < 5; ++i) h = __builtin_fma(h, u, Hc[i]);
+    const double r = __builtin_amdgcn_ldexp(__builtin_fma(T, u * h, T), (k >> LP_EXP_BITS) + v.e);
+    return v.e >= LP_NAN_E ? __builtin_nan("") : r;
+}
+
+// The evaluation part of the p node: 128 RN(p/2), s, RN(1/p) and the row-domain flag, with
+// every table read from LDS.  Device functions that are not inlined receive this part only
+// (node_eval).  Interface of the tree: leaf(a, b) and row(u, v) on the row levels' type R,
+// row_root(r) back to T, node(a, b) on T above the rows.
 template <typename T>
 struct LpEval;
 
 template <>
 struct LpEval<double> {
     using T = double;
+    using R = LpPair;
     double hp128;  // 128 RN(p/2)
+    double ia;     // RN(1/p)
     int sq;        // s: C = (Z^a')^(2^s)
-    __device__ double leaf(double a, double b) const
+    int pair;      // row levels in the logarithmic domain (1/p <= 2^20)
+    __device__ LpPair leaf(double a, double b) const
     {
-        return lp_core<true>(a, b, hp128, sq);
+        if (!pair) return LpPair{lp_core<true>(a, b, hp128, sq), 0};
+        return lp_pair_leaf(a, b, 2.0 * hp128, ia);
     }
+    __device__ LpPair row(LpPair a, LpPair b) const
+    {
+        if (!pair) return LpPair{lp_core<false>(a.l, b.l, hp128, sq), 0};
+        return lp_pair_node(a, b, 2.0 * hp128, ia);
+    }
+    __device__ double row_root(LpPair r) const { return pair ? lp_pair_value(r) : r.l; }
     __device__ double node(double a, double b) const { return lp_core<false>(a, b, hp128, sq); }
     __device__ double finish(double r) const { return r; }
 };
@@ -205,13 +318,18 @@ struct LpEval<double> {
 template <>
 struct LpEval<float> {
     using T = float;
+    using R = float;
     double hp128;  // 128 RN32(p/2)
+    double ia;     // unused (binary32 keeps the value node on every level)
     int sq;
+    int pair;
     __device__ float leaf(float a, float b) const
     {
         return (float)lp_core<true>((double)a, (double)b, hp128, sq);
     }
     __device__ float node(float a, float b) const { return (float)lp_core<false>((double)a, (double)b, hp128, sq); }
+    __device__ float row(float a, float b) const { return node(a, b); }
+    __device__ float row_root(float r) const { return r; }
     __device__ float finish(float r) const { return r; }
 };
 
@@ -228,7 +346,7 @@ struct LpNode : LpEval<T> {
 template <typename T>
 __host__ __device__ inline LpEval<T> node_eval(const LpNode<T> &nd)
 {
-    return LpEval<T>{nd.hp128, nd.sq};
+    return LpEval<T>{nd.hp128, nd.ia, nd.sq, nd.pair};
 }
 
 // Kernel-entry hook of the nodes: the p node fills its tables (the other nodes have
@@ -305,7 +423,9 @@ inline int lp_node(double half_p, double a, LpNode<T> *out)
         it = c.map.emplace(key, en).first;
     }
     out->hp128 = half_p * 128.0;
+    out->ia = a;
     out->sq = it->second.sq;
+    out->pair = sizeof(T) == 8 && a <= LP_PAIR_MAX_IA;
     memcpy(out->b, it->second.b, sizeof(out->b));
     out->rr = it->second.rr;
     return 0;

@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(TILE_WAVES * WAVE)
                     typename Node::T *res)
 {
     using T = typename Node::T;
-    __shared__ T part[Vec<T>::N][TILE_WAVES][WAVE];
+    __shared__ typename Node::R part[Vec<T>::N][TILE_WAVES][WAVE];
     node_prologue(nd);
     const int lane = threadIdx.x & (WAVE - 1);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);

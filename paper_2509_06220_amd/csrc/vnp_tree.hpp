@@ -20,6 +20,11 @@
 //   * a node whose right operand is a padding zero returns its left operand exactly, so
 //     the result equals the same tree with absent children skipped.
 //
+// The per-lane row levels (leaves included) may carry a node-specific representation R of
+// the partial norms (the binary64 p node keeps log2 of them); each row tree's root is mapped
+// back to the element type (row_root) before the columns are combined.  Every path below
+// changes representation at that same level, so the tree and its bits stay one.
+//
 // Any launch evaluates aligned power-of-two subtrees of this one tree (a wave: a tile or
 // a run of tiles; a block: a run of waves; the finish: the tree over block results), so
 // the value depends on the logical vector only.
@@ -154,17 +159,17 @@ __device__ __forceinline__ T lane_tree(const Node &nd, T t, int lane)
     return t;
 }
 
-// Merge a new subtree root `cur` at level 0 of a binary-counter stack, given that `idx`
+// Merge a new row subtree root `cur` at level 0 of a binary-counter stack, given that `idx`
 // subtrees were pushed before (idx is wave-uniform).  After the push of the last of 2^L
 // subtrees, stk[L] holds the root of all of them.
-template <class Node, typename T, int L>
-__device__ __forceinline__ void push(const Node &nd, T (&stk)[L + 1], T cur, int idx)
+template <class Node, typename R, int L>
+__device__ __forceinline__ void push(const Node &nd, R (&stk)[L + 1], R cur, int idx)
 {
     bool carry = true;
 #pragma unroll
     for (int l = 0; l < L; ++l) {
         const bool bit = (idx >> l) & 1;
-        if (carry && bit) cur = nd.node(stk[l], cur);
+        if (carry && bit) cur = nd.row(stk[l], cur);
         if (carry && !bit) stk[l] = cur;
         carry = carry && bit;
     }
@@ -204,6 +209,7 @@ __device__ __noinline__ typename Node::T tail_tile_root(Node nd, const typename 
                                                         int lane)
 {
     using T = typename Node::T;
+    using R = typename Node::R;
     using VV = Vec<T>;
     using V = typename VV::V;
     constexpr int C = VV::N;
@@ -213,37 +219,37 @@ __device__ __noinline__ typename Node::T tail_tile_root(Node nd, const typename 
     const LoadTail<T> ld{x, n, base};
     const int64_t rows = (n - base + WAVE * C - 1) / (WAVE * C);  // rows holding elements, >= 1
     const int gn = rows >= G * U ? G : (int)((rows + U - 1) / U);  // wave-uniform
-    T rstk[C][LG + 1];
+    R rstk[C][LG + 1];
 #pragma unroll 1
     for (int g = 0; g < gn; ++g) {
         V v[U];
         load_rows<U>(v, ld, g, lane);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            T w[U / 2];
+            R w[U / 2];
 #pragma unroll
             for (int u = 0; u < U / 2; ++u) w[u] = nd.leaf(VV::get(v[2 * u], c), VV::get(v[2 * u + 1], c));
 #pragma unroll
             for (int s = U / 4; s >= 1; s >>= 1) {
 #pragma unroll
-                for (int u = 0; u < s; ++u) w[u] = nd.node(w[2 * u], w[2 * u + 1]);
+                for (int u = 0; u < s; ++u) w[u] = nd.row(w[2 * u], w[2 * u + 1]);
             }
-            push<Node, T, LG>(nd, rstk[c], w[0], g);
+            push<Node, R, LG>(nd, rstk[c], w[0], g);
         }
     }
     T col[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        T cur = T(0);
+        R cur = rstk[c][0];  // gn >= 1: some level below is filled
         bool any = false;
 #pragma unroll
         for (int l = 0; l <= LG; ++l) {
             if ((gn >> l) & 1) {
-                cur = any ? nd.node(rstk[c][l], cur) : rstk[c][l];
+                cur = any ? nd.row(rstk[c][l], cur) : rstk[c][l];
                 any = true;
             }
         }
-        col[c] = cur;
+        col[c] = nd.row_root(cur);
     }
     T r;
     if constexpr (C == 2) {
@@ -278,6 +284,7 @@ __device__ __forceinline__ typename Node::T wave_root_with(const Node &nd, const
                                                            int lane, bool &nan_tile)
 {
     using T = typename Node::T;
+    using R = typename TN::R;
     using VV = Vec<T>;
     using V = typename VV::V;
     constexpr int C = VV::N;
@@ -291,7 +298,7 @@ __device__ __forceinline__ typename Node::T wave_root_with(const Node &nd, const
     const int ktiles = left < ((int64_t)1 << lwt) ? (int)left : (1 << lwt);
     const int Q = ktiles * G;  // row groups to reduce (even)
 
-    T rstk[C][LG + 1];
+    R rstk[C][LG + 1];
     T tstk[MAX_LWT + 1];
 
     // binary counter over tile roots; entries stay wave-uniform.  After the last of
@@ -312,22 +319,25 @@ __device__ __forceinline__ typename Node::T wave_root_with(const Node &nd, const
         const int g = q & (G - 1);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            T w[U / 2];
+            R w[U / 2];
 #pragma unroll
             for (int u = 0; u < U / 2; ++u) w[u] = tn.leaf(VV::get(v[2 * u], c), VV::get(v[2 * u + 1], c));
 #pragma unroll
             for (int s = U / 4; s >= 1; s >>= 1) {
 #pragma unroll
-                for (int u = 0; u < s; ++u) w[u] = tn.node(w[2 * u], w[2 * u + 1]);
+                for (int u = 0; u < s; ++u) w[u] = tn.row(w[2 * u], w[2 * u + 1]);
             }
-            push<TN, T, LG>(tn, rstk[c], w[0], g);
+            push<TN, R, LG>(tn, rstk[c], w[0], g);
         }
         if (g == G - 1) {
+            T col[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) col[c] = tn.row_root(rstk[c][LG]);
             T t;
             if constexpr (C == 2) {
-                t = tn.node(rstk[0][LG], rstk[1][LG]);
+                t = tn.node(col[0], col[1]);
             } else {
-                t = tn.node(tn.node(rstk[0][LG], rstk[1][LG]), tn.node(rstk[2][LG], rstk[3][LG]));
+                t = tn.node(tn.node(col[0], col[1]), tn.node(col[2], col[3]));
             }
             const T root = uniform(lane_tree(tn, t, lane));
             if constexpr (!std::is_same<TN, Node>::value) nan_tile = nan_tile || root != root;
@@ -426,9 +436,10 @@ constexpr int WAVE_ROWS = ROWS / TILE_WAVES;
 template <class Node, bool FAST>
 __device__ __forceinline__ typename Node::T tile_root_block(
     const Node &nd, const typename Node::T *x, int64_t n, Stride sd, int64_t t, int lane, int w,
-    typename Node::T (&part)[Vec<typename Node::T>::N][TILE_WAVES][WAVE])
+    typename Node::R (&part)[Vec<typename Node::T>::N][TILE_WAVES][WAVE])
 {
     using T = typename Node::T;
+    using R = typename Node::R;
     using VV = Vec<T>;
     using V = typename VV::V;
     constexpr int C = VV::N;
@@ -452,20 +463,20 @@ __device__ __forceinline__ typename Node::T tile_root_block(
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        T a[WAVE_ROWS / 2];
+        R a[WAVE_ROWS / 2];
 #pragma unroll
         for (int u = 0; u < WAVE_ROWS / 2; ++u) a[u] = nd.leaf(VV::get(v[2 * u], c), VV::get(v[2 * u + 1], c));
-        part[c][w][lane] = nd.node(nd.node(a[0], a[1]), nd.node(a[2], a[3]));
+        part[c][w][lane] = nd.row(nd.row(a[0], a[1]), nd.row(a[2], a[3]));
     }
     __syncthreads();
     T col[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        T b[TILE_WAVES];
+        R b[TILE_WAVES];
 #pragma unroll
         for (int j = 0; j < TILE_WAVES; ++j) b[j] = part[c][j][lane];
-        col[c] = nd.node(nd.node(nd.node(b[0], b[1]), nd.node(b[2], b[3])),
-                         nd.node(nd.node(b[4], b[5]), nd.node(b[6], b[7])));
+        col[c] = nd.row_root(nd.row(nd.row(nd.row(b[0], b[1]), nd.row(b[2], b[3])),
+                                    nd.row(nd.row(b[4], b[5]), nd.row(b[6], b[7]))));
     }
     T r;
     if constexpr (C == 2) {

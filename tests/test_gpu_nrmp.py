@@ -162,3 +162,47 @@ def test_pnorm_launch_shapes_are_bitwise_identical(fmt):
             assert gpu_p(x, 3.0) == ref
     finally:
         vnp.set_launch_shape(0, 0)
+
+
+@pytest.mark.parametrize("p", [3.0, 0.5, 2.0 ** -20, 2.0 ** -21])
+def test_pnode_row_classes(p):
+    """Zeros, infinities, NaN and overflow through the binary64 row levels, which carry
+    log2 of each partial norm (1/p <= 2^20) or the value itself (1/p > 2^20): zero runs
+    stay exact, NaN beats inf wherever each one sits, an overflowing norm is +inf.  One
+    nonzero element among zeros gives its magnitude (Sect. 4's node with Q = 0 is exact):
+    bitwise in the value domain, and within the rounding of 2^l at the row root (2 eps) in
+    the logarithmic one."""
+    n = 3 * 8192 + 517  # several tiles and a ragged tail tile
+    z = np.zeros(n)
+    assert gpu_p(to_dev(z), p) == 0.0
+    for i in [0, 1, 63, 4097, n - 1]:
+        y = z.copy()
+        y[i] = -1.2345e-300 if i % 2 else 6.5e305
+        g = gpu_p(to_dev(y), p)
+        if p < 2.0 ** -20:
+            assert g == abs(y[i]), (p, i)
+        else:
+            assert abs(g - abs(y[i])) <= 2 * 2.0 ** -53 * abs(y[i]), (p, i, g)
+    y = z.copy()
+    y[[5, 9000]] = [1.5, -2.0]
+    if p < 2.0 ** -19:  # |x|^p ~ 1 for both: (1 + 1)^(1/p) overflows
+        assert gpu_p(to_dev(y), p) == math.inf
+    else:
+        assert_parity(gpu_p(to_dev(y), p), oracle.nrmp(y, p), n, "f64", f"p={p}")
+    w = vnp_gen.host_fill(n, dtype="f64", kind="exp", lo=-10, hi=10, seed=21)
+    w[::7] = 0.0
+    v = w.copy()
+    v[8191] = np.inf
+    assert gpu_p(to_dev(v), p) == math.inf
+    v[20000] = np.nan  # another tile than the infinity
+    assert math.isnan(gpu_p(to_dev(v), p))
+    v = w.copy()
+    v[3] = np.nan
+    v[n - 2] = -np.inf
+    assert math.isnan(gpu_p(to_dev(v), p))
+    big = np.full(4096, 1.0e308)
+    assert gpu_p(to_dev(big), p) == math.inf
+    if p >= 0.5:
+        assert_parity(gpu_p(to_dev(w), p), oracle.nrmp(w, p), n, "f64", f"p={p}")
+        sub = w * 1e-310  # subnormal elements and partial norms
+        assert_parity(gpu_p(to_dev(sub), p), oracle.nrmp(sub, p), n, "f64", f"p={p} subnormal")
