@@ -414,9 +414,11 @@ int64_t vnp_tile_elems(int dtype)
 
 uint32_t vnp_tree_id(int dtype)
 {
-    // bits 0..7: log2(tile elements); 8..11: rows log2; 12..15: node version; 16: dtype
+    // bits 0..7: log2(tile elements); 8..11: rows log2; 12..15: node version (3: the
+    // p node's logarithm table exact at 1/2 and, in binary64, its row levels in log2);
+    // 16: dtype
     const uint32_t te = dtype == VNP_F32 ? 14u : 13u;
-    return te | (6u << 8) | (2u << 12) | ((uint32_t)(dtype == VNP_F32) << 16);
+    return te | (6u << 8) | (3u << 12) | ((uint32_t)(dtype == VNP_F32) << 16);
 }
 
 const char *vnp_version(void) { return "vnp 0.1 (gfx950)"; }
