@@ -4,7 +4,7 @@ Chebyshev interpolation in 60-digit arithmetic (a near-minimax fit), then roundi
 binary64; prints each polynomial's largest error, evaluated by Horner's rule in exact
 arithmetic on a dense grid, and writes the tables and coefficients to vnp_lp_table.hpp:
 
-* log2 f for f in [1/2, 1): 2^LOG_BITS intervals, entry {c_j, l_j} with c_j = RN(1/mid_j)
+* log2 f for f in [1/2, 1]: 2^LOG_BITS intervals and f = 1, entry {c_j, l_j} with c_j = RN(1/mid_j)
   and l_j = RN(log2(2/c_j)), except entry 0, which takes the interval's left end:
   c_0 = 2, l_0 = 0, so that f = 1/2 gives t = 0 and log2(2 f) = 0 exactly; then
   log2 f = (l_j - 1) + log2(1 + t), t = f c_j - 1, and log2(1 + t) = t g(t), with g fitted
@@ -66,6 +66,7 @@ def log_table():
         rows.append((c, float(mp.log(2 / mp.mpf(c), 2))))
         # every f of the interval has |f c_j - 1| <= T_MAX
         assert max(abs(lo * mp.mpf(c) - 1), abs(hi * mp.mpf(c) - 1)) <= T_MAX
+    rows.append((1.0, 1.0))  # f = 1 (index 2^LOG_BITS, with the exponent's low bit): log2(2 f) = 1
     return rows
 
 
@@ -114,7 +115,8 @@ def main():
         fh.write(f"// RN(1 / mid_j), mid_j = 1/2 + (j + 1/2) / {2 ** (LOG_BITS + 1)}, l_j = RN(log2(2 / c_j)), "
                  f"except c_0 = 2, l_0 = 0\n// (the left end: log2(2 f) = 0 exactly at f = 1/2); "
                  f"log2(1 + t) = t g(t), -1.01 * 2^-{LOG_BITS + 1} <= t <=\n// 1.01 * 2^-{LOG_BITS}, "
-                 f"g of degree {LOG_DEG} (absolute error 2^{mp.nstr(mp.log(wg, 2), 3)}).\n")
+                 f"g of degree {LOG_DEG} (absolute error 2^{mp.nstr(mp.log(wg, 2), 3)}).  Entry {2 ** LOG_BITS} "
+                 f"(f = 1, picked\n// through the exponent's low bit) is {{1, 1}}: log2(2 f) = 1 exactly.\n")
         fh.write(f"// 2^y: entry j is T_j = RN(2^(j / {2 ** EXP_BITS})); 2^(u / {2 ** EXP_BITS}) - 1 = u H(u), "
                  f"|u| <= 1/2, H of degree\n// {EXP_DEG} (relative error 2^{mp.nstr(mp.log(wh, 2), 3)}).\n")
         fh.write(f"// Z^a: entry j (the top {POW_BITS} fraction bits of Z in [1, 2)) is c'_j = "
@@ -123,7 +125,7 @@ def main():
         fh.write("#pragma once\n\nnamespace vnp {\n\n")
         fh.write(f"constexpr int LP_LOG_BITS = {LOG_BITS};\nconstexpr int LP_EXP_BITS = {EXP_BITS};\n"
                  f"constexpr int LP_POW_BITS = {POW_BITS};\nconstexpr int LP_POW_TERMS = {POW_TERMS};\n")
-        fh.write("static __constant__ double lp_log_src[1 << LP_LOG_BITS][2] = {\n")
+        fh.write("static __constant__ double lp_log_src[(1 << LP_LOG_BITS) + 1][2] = {\n")
         for c, l in lrows:
             fh.write(f"    {{{c.hex()}, {l.hex()}}},\n")
         fh.write("};\n")

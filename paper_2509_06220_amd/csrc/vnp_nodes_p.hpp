@@ -65,34 +65,37 @@ constexpr int LP_POW_N = 1 << LP_POW_BITS;
 constexpr int LP_B_N = 8;  // binomial coefficient slots (LP_POW_TERMS used)
 constexpr double LP_RHO0 = 0x1p-1074;  // rho_0 (see above)
 
-// The tables in LDS, one copy per block, filled by lp_table_fill at kernel entry.
-__device__ __forceinline__ double2 *lp_log_lds()  // {c_j, l_j}
-{
-    __shared__ double2 tab[LP_LOG_N];
-    return tab;
-}
-__device__ __forceinline__ double *lp_exp_lds()  // T_j
-{
-    __shared__ double tab[LP_EXP_N];
-    return tab;
-}
+// The tables in LDS, one copy per block, filled by lp_table_fill at kernel entry, in one
+// arena: the log2 table first (1025 entries), then 2^(j/128), the power table and the
+// coefficients.  log2_p1 indexes with the exponent's low bit, so the mantissa of a NaN
+// (from two NaN operands, whose result is replaced) picks an index in [1024, 2048): the
+// arena spans more than 2048 log2 entries, so that read stays inside it.
 struct PowEntry {
     double R, rho, c, pad;
 };
-__device__ __forceinline__ PowEntry *lp_pow_lds()  // {R_j, rho_j, c'_j}
-{
-    __shared__ PowEntry tab[LP_POW_N];
-    return tab;
-}
 // Polynomial coefficients: g (4), H (5), then the binomial coefficients b_1 .. b_5 (and
 // zeros).  Read at one address in all lanes: as scalar operands they would exhaust the
 // scalar registers, and two scalar operands of one fma cost an extra vector move.
 constexpr int LP_G_OFF = 0, LP_H_OFF = 4, LP_BC_OFF = 9;
-__device__ __forceinline__ double *lp_coef_lds()
+constexpr int LP_LOG_BYTES = (LP_LOG_N + 1) * 16;
+constexpr int LP_EXP_AT = LP_LOG_BYTES;
+constexpr int LP_POW_AT = LP_EXP_AT + LP_EXP_N * 8;
+constexpr int LP_COEF_AT = LP_POW_AT + LP_POW_N * (int)sizeof(PowEntry);
+constexpr int LP_ARENA_BYTES = LP_COEF_AT + (LP_BC_OFF + LP_B_N) * 8;
+static_assert(LP_ARENA_BYTES >= 2 * LP_LOG_N * 16 && LP_POW_AT % 16 == 0 && LP_COEF_AT % 16 == 0,
+              "arena layout");
+__device__ __forceinline__ unsigned char *lp_arena()
 {
-    __shared__ double tab[LP_BC_OFF + LP_B_N];
-    return tab;
+    __shared__ __attribute__((aligned(16))) unsigned char arena[LP_ARENA_BYTES];
+    return arena;
 }
+__device__ __forceinline__ double2 *lp_log_lds() { return reinterpret_cast<double2 *>(lp_arena()); }  // {c_j, l_j}
+__device__ __forceinline__ double *lp_exp_lds() { return reinterpret_cast<double *>(lp_arena() + LP_EXP_AT); }  // T_j
+__device__ __forceinline__ PowEntry *lp_pow_lds()  // {R_j, rho_j, c'_j}
+{
+    return reinterpret_cast<PowEntry *>(lp_arena() + LP_POW_AT);
+}
+__device__ __forceinline__ double *lp_coef_lds() { return reinterpret_cast<double *>(lp_arena() + LP_COEF_AT); }
 
 // Every thread of the block calls this before the first node evaluation.  rr: the per-p
 // device table (R_0 .. R_511, rho_0 .. rho_511); b: the binomial coefficients.
@@ -101,7 +104,7 @@ __device__ __forceinline__ void lp_table_fill(const double *rr, const double *b)
     double2 *lt = lp_log_lds();
     double *et = lp_exp_lds();
     PowEntry *pt = lp_pow_lds();
-    for (int i = threadIdx.x; i < LP_LOG_N; i += blockDim.x) lt[i] = make_double2(lp_log_src[i][0], lp_log_src[i][1]);
+    for (int i = threadIdx.x; i <= LP_LOG_N; i += blockDim.x) lt[i] = make_double2(lp_log_src[i][0], lp_log_src[i][1]);
     for (int i = threadIdx.x; i < LP_EXP_N; i += blockDim.x) et[i] = lp_exp_src[i];
     for (int i = threadIdx.x; i < LP_POW_N; i += blockDim.x)
         pt[i] = PowEntry{rr[i], rr[LP_POW_N + i], lp_pow_src[i], 0.0};
@@ -112,11 +115,11 @@ __device__ __forceinline__ void lp_table_fill(const double *rr, const double *b)
     __syncthreads();
 }
 
-// log2 f + 1 for f in [1/2, 1).
+// log2 f + 1 for f in [1/2, 1] (the exponent's low bit selects entry LP_LOG_N for f = 1).
 __device__ __forceinline__ double log2_p1(double f)
 {
     const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(f) >> 32);
-    const double2 e = lp_log_lds()[(hi >> (20 - LP_LOG_BITS)) & (LP_LOG_N - 1)];
+    const double2 e = lp_log_lds()[(hi >> (20 - LP_LOG_BITS)) & (2 * LP_LOG_N - 1)];
     const double t = __builtin_fma(f, e.x, -1.0);
     const double *G = lp_coef_lds() + LP_G_OFF;
     double g = G[0];
@@ -233,10 +236,8 @@ __device__ __forceinline__ LpPair lp_pair_tail(double d, double lM, int eM, doub
 {
     const double y = __builtin_fmax(-p128 * __builtin_fabs(d), -2100.0 * 128);
     const double S2 = exp2_tab(y);
-    // (1 + S^2)/2 in [1/2, 1]; 1 (m = M) is taken as its predecessor, within the rounding
-    // of the sum
-    const double Zh = __builtin_fmin(__builtin_fma(S2, 0.5, 0.5), 0x1.fffffffffffffp-1);
-    const double lr = __builtin_fma(ia, log2_p1(Zh), lM);  // >= 0
+    // (1 + S^2)/2 in [1/2, 1] (S^2 <= 1 since y <= 0)
+    const double lr = __builtin_fma(ia, log2_p1(__builtin_fma(S2, 0.5, 0.5)), lM);  // >= 0
     return LpPair{__builtin_amdgcn_fract(lr), eM + (int)lr};  // (int) truncates: floor
 }
 
