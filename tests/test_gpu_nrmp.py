@@ -206,3 +206,37 @@ def test_pnode_row_classes(p):
         assert_parity(gpu_p(to_dev(w), p), oracle.nrmp(w, p), n, "f64", f"p={p}")
         sub = w * 1e-310  # subnormal elements and partial norms
         assert_parity(gpu_p(to_dev(sub), p), oracle.nrmp(sub, p), n, "f64", f"p={p} subnormal")
+
+
+@pytest.mark.parametrize("p", [3.0, 0.5])
+def test_pnode_row_classes_streamed(p):
+    """The same classes through the streaming kernel (enough tiles for it; a ragged tail
+    tile evaluated out of line) and through the batched kernel: zeros in whole row groups,
+    an infinity or a NaN in a streamed tile and in the tail tile, and one nonzero element
+    among zeros; each streamed result equals the batched one for the same segment."""
+    te = 8192
+    n = 1100 * te + 517  # above the small-vector limit of 4 tiles per CU (256 CUs)
+    w = vnp_gen.host_fill(n, dtype="f64", kind="exp", lo=-10, hi=10, seed=31)
+    w[1000:5000] = 0.0  # zero row groups inside a streamed tile
+    w[n - 300:] = 0.0  # the tail tile ends in zeros
+    cases = {"finite": w}
+    v = w.copy(); v[777 * te + 4321] = np.inf; cases["inf streamed"] = v
+    v = w.copy(); v[n - 400] = -np.inf; cases["inf tail"] = v
+    v = w.copy(); v[5 * te + 1] = np.nan; v[n - 350] = np.inf; cases["nan streamed, inf tail"] = v
+    v = w.copy(); v[n - 450] = np.nan; v[3] = np.inf; cases["inf streamed, nan tail"] = v
+    z = np.zeros(n); z[600 * te + 77] = -3.25e-200; cases["one nonzero"] = z
+    for name, x in cases.items():
+        d = to_dev(x)
+        g = gpu_p(d, p)
+        off = torch.tensor([0, n], dtype=torch.int64, device="cuda")
+        gb = vnp.nrm_batched(d, off, p=p).item()
+        print(f"p={p} {name}: {g!r} batched {gb!r}", flush=True)
+        assert (math.isnan(g) and math.isnan(gb)) or g == gb, (name, g, gb)
+        if name == "finite":
+            assert_parity(g, oracle.nrmp(x, p), n, "f64", f"p={p} {name}")
+        elif "nan" in name:
+            assert math.isnan(g), name
+        elif "inf" in name:
+            assert g == math.inf, name
+        else:
+            assert abs(g - 3.25e-200) <= 2 * 2.0 ** -53 * 3.25e-200, (name, g)
