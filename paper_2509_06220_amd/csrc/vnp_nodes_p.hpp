@@ -250,7 +250,14 @@ __device__ __forceinline__ LpPair lp_pair_node(LpPair a, LpPair b, double p128, 
 }
 
 // Leaf on two elements (signs allowed): log2 |a|, log2 |b| from the log2 table, then the
-// row node.
+// row node.  Zeros and non-finite operands are fixed up afterwards, in a branch that only a
+// wave holding one takes (a wave-uniform test, then per-lane choices); the common path
+// spends three compares on them.  The fix-ups give what the arithmetic with m's exponent
+// taken as that of +0 (S^2 = 0) gives:
+//   m = 0 < M: node(M, 0) = M, the pair of log2 M (l and e from lM and eM exactly);
+//   M = 0:     +0, e = LP_ZERO_E (with l from the same lM, a finite value);
+//   an infinite or NaN operand: l = 0 and the class's e (the logarithm of inf is not
+//   finite).
 __device__ __forceinline__ LpPair lp_pair_leaf(double a, double b, double p128, double ia)
 {
     double M, m;
@@ -260,13 +267,15 @@ __device__ __forceinline__ LpPair lp_pair_leaf(double a, double b, double p128, 
     const double lm = log2_p1(__builtin_amdgcn_frexp_mant(m));
     // frexp's exponents are one above those of the mantissa in [1, 2); equal offsets cancel
     const int eM = __builtin_amdgcn_frexp_exp(M);
-    const int em = m > 0.0 ? __builtin_amdgcn_frexp_exp(m) : LP_ZERO_E;
+    const int em = __builtin_amdgcn_frexp_exp(m);
     LpPair r = lp_pair_tail((double)(em - eM) + (lm - lM), lM, eM - 1, p128, ia);
-    // both zero: the e of +0 (l stays finite: the table at f = 0 gives a finite value)
-    r.e = M > 0.0 ? r.e : LP_ZERO_E;
-    // an infinite or NaN operand: l = 0 (the logarithm of inf is not finite) and the class's e
     const bool nan = __builtin_isunordered(a, b);
-    if (nan || __builtin_isinf(M)) r = LpPair{0.0, nan ? LP_NAN_E : LP_INF_E};
+    const bool inf = __builtin_isinf(M);
+    const bool zero = !(m > 0.0);
+    if (__builtin_amdgcn_ballot_w64(nan || inf || zero) != 0) {
+        if (zero) r = LpPair{__builtin_amdgcn_fract(lM), M > 0.0 ? eM - 1 + (int)lM : LP_ZERO_E};
+        if (nan || inf) r = LpPair{0.0, nan ? LP_NAN_E : LP_INF_E};
+    }
     return r;
 }
 
