@@ -192,18 +192,19 @@ __device__ __forceinline__ double lp_core(double a, double b, double hp128, int 
 }
 
 // ---------------------------------------------------------------------------------
-// The row levels of the binary64 p node in the logarithmic domain.
+// The levels inside a tile of the binary64 p node in the logarithmic domain.
 //
-// The per-lane row tree (the lowest six levels, 63 of every 64 nodes) carries each partial
-// norm v as a pair (l, e) with v = 2^(e + l), l in [0, 1) and e an integer.  Its node is
+// Inside a tile (the per-lane rows with the leaves, the columns and the lanes: 8191 of every
+// 8192 nodes) each partial norm v is carried as a pair (l, e) with v = 2^(e + l), l in
+// [0, 1) and e an integer.  The node on these levels ("row" node) is
 // Sect. 4's node(a, b) = M (1 + Q^p)^(1/p) with the logarithm taken of both sides:
 //     log2 node = log2 M + (1/p) log2(1 + 2^(p d)),  d = log2 m - log2 M = -|log2 a - log2 b|,
 // with 2^(p d) = S^2 = Q^(2 RN(p/2)) and 1/p = RN(1/p) (the exponents rounded once, Sect. 4).
 // An internal row node therefore needs no logarithm of its operands and no power: one 2^y
 // (the table above, y = 128 p d), one log2(1 + S^2) (the log2 table at (1 + S^2)/2, whose
 // rounding is that of Z = fma(S, S, 1)), and an fma; a leaf takes the logarithms of its two
-// elements first.  The row root goes back to a value, 2^l scaled by 2^e, and the levels above
-// (columns, lanes, tiles, runs, blocks) use the value node lp_core.
+// elements first.  The tile root goes back to a value, 2^l scaled by 2^e, and the levels
+// above (tiles, runs, blocks) use the value node lp_core.
 //
 // Exactness and special values:
 //   * node(v, 0) = v exactly: a zero operand gives S^2 = 0, (1 + S^2)/2 = 1/2, whose log2
@@ -212,8 +213,8 @@ __device__ __forceinline__ double lp_core(double a, double b, double hp128, int 
 //   * +0 is e <= -2^29 (LP_ZERO_E = -2^30), +inf e in [2^27, 2^29) (LP_INF_E), NaN e >= 2^29
 //     (LP_NAN_E), each with l = 0, set by the leaves.  The row node orders such pairs like
 //     the values they stand for (NaN above inf above every finite value above +0), and a
-//     level moves e by at most 1/p + 1, so six levels keep every class apart while
-//     1/p <= 2^20 (for larger 1/p, i.e. p below about 9.5e-7, the node stays in the value
+//     level moves e by at most 1/p + 1, so the thirteen levels of a tile keep every class
+//     apart while 1/p <= 2^20 (for larger 1/p, i.e. p below about 9.5e-7, the node stays in the value
 //     domain: the uniform flag `pair`).  The conversion to a value maps e beyond the
 //     binary64 range to +inf or +0 by ldexp, and NaN pairs to NaN.
 //   * Errors per row node: the two table functions (2^-54 each, absolute in log2), the
@@ -224,6 +225,8 @@ struct LpPair {
     double l;  // in [0, 1)
     int e;
 };
+// exchange of a pair between lanes (the lane levels of a tile)
+__device__ __forceinline__ LpPair xshfl(LpPair v, int s) { return LpPair{__shfl_xor(v.l, s), __shfl_xor(v.e, s)}; }
 constexpr int LP_ZERO_E = -(1 << 30);
 constexpr int LP_INF_E = 1 << 28;
 constexpr int LP_NAN_E = 1 << 29;

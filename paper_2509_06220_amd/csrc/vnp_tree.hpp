@@ -20,10 +20,11 @@
 //   * a node whose right operand is a padding zero returns its left operand exactly, so
 //     the result equals the same tree with absent children skipped.
 //
-// The per-lane row levels (leaves included) may carry a node-specific representation R of
-// the partial norms (the binary64 p node keeps log2 of them); each row tree's root is mapped
-// back to the element type (row_root) before the columns are combined.  Every path below
-// changes representation at that same level, so the tree and its bits stay one.
+// The levels inside a tile (per-lane rows with the leaves, columns, lanes) may carry a
+// node-specific representation R of the partial norms (the binary64 p node keeps log2 of
+// them); each tile root is mapped back to the element type (row_root) before the tiles are
+// combined.  Every path below changes representation at that same level, so the tree and
+// its bits stay one.
 //
 // Any launch evaluates aligned power-of-two subtrees of this one tree (a wave: a tile or
 // a run of tiles; a block: a run of waves; the finish: the tree over block results), so
@@ -159,6 +160,21 @@ __device__ __forceinline__ T lane_tree(const Node &nd, T t, int lane)
     return t;
 }
 
+// The same butterfly on a tile's levels in the row representation R (row nodes; the
+// exchange of a non-scalar R is an overload of xshfl found with R).  Each lane takes its own
+// value as the left operand: lane 0 is the lower lane at every level, so its result is the
+// ordered tree's, and the kernels read the tile root from lane 0 (every node here is also
+// symmetric bitwise, so the other lanes hold the same value).
+__device__ __forceinline__ double xshfl(double v, int s) { return __shfl_xor(v, s); }
+__device__ __forceinline__ float xshfl(float v, int s) { return __shfl_xor(v, s); }
+template <class Node, typename R>
+__device__ __forceinline__ R lane_tree_rows(const Node &nd, R t, int)
+{
+#pragma unroll
+    for (int s = 1; s < WAVE; s <<= 1) t = nd.row(t, xshfl(t, s));
+    return t;
+}
+
 // Merge a new row subtree root `cur` at level 0 of a binary-counter stack, given that `idx`
 // subtrees were pushed before (idx is wave-uniform).  After the push of the last of 2^L
 // subtrees, stk[L] holds the root of all of them.
@@ -237,7 +253,7 @@ __device__ __noinline__ typename Node::T tail_tile_root(Node nd, const typename 
             push<Node, R, LG>(nd, rstk[c], w[0], g);
         }
     }
-    T col[C];
+    R col[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         R cur = rstk[c][0];  // gn >= 1: some level below is filled
@@ -249,15 +265,15 @@ __device__ __noinline__ typename Node::T tail_tile_root(Node nd, const typename 
                 any = true;
             }
         }
-        col[c] = nd.row_root(cur);
+        col[c] = cur;
     }
-    T r;
+    R r;
     if constexpr (C == 2) {
-        r = nd.node(col[0], col[1]);
+        r = nd.row(col[0], col[1]);
     } else {
-        r = nd.node(nd.node(col[0], col[1]), nd.node(col[2], col[3]));
+        r = nd.row(nd.row(col[0], col[1]), nd.row(col[2], col[3]));
     }
-    return lane_tree(nd, r, lane);
+    return nd.row_root(lane_tree_rows(nd, r, lane));
 }
 
 constexpr int MAX_LWT = 12;  // a wave covers at most 2^12 tiles
@@ -330,16 +346,13 @@ __device__ __forceinline__ typename Node::T wave_root_with(const Node &nd, const
             push<TN, R, LG>(tn, rstk[c], w[0], g);
         }
         if (g == G - 1) {
-            T col[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) col[c] = tn.row_root(rstk[c][LG]);
-            T t;
+            R t;
             if constexpr (C == 2) {
-                t = tn.node(col[0], col[1]);
+                t = tn.row(rstk[0][LG], rstk[1][LG]);
             } else {
-                t = tn.node(tn.node(col[0], col[1]), tn.node(col[2], col[3]));
+                t = tn.row(tn.row(rstk[0][LG], rstk[1][LG]), tn.row(rstk[2][LG], rstk[3][LG]));
             }
-            const T root = uniform(lane_tree(tn, t, lane));
+            const T root = uniform(tn.row_root(lane_tree_rows(tn, t, lane)));
             if constexpr (!std::is_same<TN, Node>::value) nan_tile = nan_tile || root != root;
             push_tile(root, q >> LG);
         }
@@ -469,22 +482,21 @@ __device__ __forceinline__ typename Node::T tile_root_block(
         part[c][w][lane] = nd.row(nd.row(a[0], a[1]), nd.row(a[2], a[3]));
     }
     __syncthreads();
-    T col[C];
+    R col[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         R b[TILE_WAVES];
 #pragma unroll
         for (int j = 0; j < TILE_WAVES; ++j) b[j] = part[c][j][lane];
-        col[c] = nd.row_root(nd.row(nd.row(nd.row(b[0], b[1]), nd.row(b[2], b[3])),
-                                    nd.row(nd.row(b[4], b[5]), nd.row(b[6], b[7]))));
+        col[c] = nd.row(nd.row(nd.row(b[0], b[1]), nd.row(b[2], b[3])), nd.row(nd.row(b[4], b[5]), nd.row(b[6], b[7])));
     }
-    T r;
+    R r;
     if constexpr (C == 2) {
-        r = nd.node(col[0], col[1]);
+        r = nd.row(col[0], col[1]);
     } else {
-        r = nd.node(nd.node(col[0], col[1]), nd.node(col[2], col[3]));
+        r = nd.row(nd.row(col[0], col[1]), nd.row(col[2], col[3]));
     }
-    return lane_tree(nd, r, lane);
+    return nd.row_root(lane_tree_rows(nd, r, lane));
 }
 
 // Tree over v[0..m) (m a power of two) held in LDS, pairs at growing strides; the root
