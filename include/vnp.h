@@ -94,10 +94,10 @@ int vnp_dnrmf_noalloc(int64_t n, const double *x, int64_t incx, double *res, voi
 /* p-norm.  p = 1 uses |a| + |b| nodes (Eq. (vp1)); p = +inf, and p at or above the
  * cutoff of Sect. 4 (2^53 for D, 2^24 for S), use max(|a|, |b|) (Eq. (vpI)); p = 2 uses
  * the Frobenius node; other p > 0 use the node of Listing 5 (0 < p < 1 gives the
- * quasi-norm of Sect. 4).  In binary64 the lowest six levels of every lane evaluate that
- * node on log2 of the partial norms (the same rounded exponents RN(p/2), RN(1/p)), the
- * levels above on the values; the relative error of one node stays below
- * 4 max(1, 1/p) eps. */
+ * quasi-norm of Sect. 4).  In binary64 the levels inside each tile of the tree (8191 of
+ * every 8192 nodes) evaluate that node on log2 of the partial norms (the same rounded
+ * exponents RN(p/2), RN(1/p)), the levels above on the values; the relative error of one
+ * node stays below 4 max(1, 1/p) eps. */
 int vnp_dnrmp(int64_t n, const double *x, int64_t incx, double p, double *res, void *stream);
 int vnp_snrmp(int64_t n, const float *x, int64_t incx, float p, float *res, void *stream);
 

@@ -4,6 +4,7 @@ stand-in inputs; Table 4 of Sect. 5 for p != 2), against the GPU results that
 any host, takes hours at the paper's sizes, and is not collected by pytest.
 
     python tests/accuracy_study.py GPU_JSON [--part frobenius|pnorm|all] [--pa-log2 22]
+                                   [--ref-cache FILE]
 
 Frobenius: relerr (Eq. (relerr), multiples of eps) against the exact norm, for the GPU
 results and the oracle's A, H, Z and Theorem 1's single accumulator on the same inputs.
@@ -56,22 +57,38 @@ def frobenius(g):
             "frobenius": out}
 
 
-def pnorm(g, pa_log2):
+def pnorm(g, pa_log2, cache_path=None):
+    """cache_path: a JSON file of the oracle's values per (p, seed) and sizes (the binary128
+    references and A_p, as hex strings): read if present, written as they are computed, so
+    that new GPU results are compared again without recomputing them."""
     pn_n, pseeds = g["pnorm_n"], g["pnorm_seeds"]
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        with open(cache_path) as f:
+            cache = json.load(f)
     out = {}
     for name, p in bench.STUDY_PS.items():
         e = {"gpu_flat": [], "gpu_rec": [], "A_flat": [], "A_rec": []}
         for sd in range(pseeds):
             t0 = time.time()
-            x = vnp_gen.host_fill(pn_n, kind="u01", seed=sd, stream=61)
+            key = f"{name} seed {sd} n {pn_n} pa {1 << pa_log2}"
+            if key not in cache:
+                x = vnp_gen.host_fill(pn_n, kind="u01", seed=sd, stream=61)
+                flat, rec = sum(oracle.ref_pnorm(x, p)), sum(oracle.ref_pnorm_R(x, p))
+                xs = np.ascontiguousarray(x[:1 << pa_log2])
+                del x
+                vals = [flat, rec, oracle.nrmp(xs, p, "A"), sum(oracle.ref_pnorm(xs, p)), sum(oracle.ref_pnorm_R(xs, p))]
+                cache[key] = [float(v).hex() for v in vals]
+                if cache_path:
+                    with open(cache_path + ".tmp", "w") as f:
+                        json.dump(cache, f)
+                    os.replace(cache_path + ".tmp", cache_path)
+            flat, rec, o, aflat, arec = (float.fromhex(v) for v in cache[key])
             gv = float.fromhex(g["pnorm"][name][sd])
-            e["gpu_flat"].append(oracle.relerr(gv, sum(oracle.ref_pnorm(x, p)), "f64"))
-            e["gpu_rec"].append(oracle.relerr(gv, sum(oracle.ref_pnorm_R(x, p)), "f64"))
-            xs = np.ascontiguousarray(x[:1 << pa_log2])
-            del x
-            o = oracle.nrmp(xs, p, "A")
-            e["A_flat"].append(oracle.relerr(o, sum(oracle.ref_pnorm(xs, p)), "f64"))
-            e["A_rec"].append(oracle.relerr(o, sum(oracle.ref_pnorm_R(xs, p)), "f64"))
+            e["gpu_flat"].append(oracle.relerr(gv, flat, "f64"))
+            e["gpu_rec"].append(oracle.relerr(gv, rec, "f64"))
+            e["A_flat"].append(oracle.relerr(o, aflat, "f64"))
+            e["A_rec"].append(oracle.relerr(o, arec, "f64"))
             print(f"accuracy study: p={name} seed {sd} ({time.time() - t0:.1f} s) " +
                   " ".join(f"{k}={v[-1]:.3f}" for k, v in e.items()), file=sys.stderr, flush=True)
         out[name] = {k: {"max": round(max(v), 4), "mean": round(sum(v) / len(v), 4)} for k, v in e.items()}
@@ -83,6 +100,7 @@ def main():
     ap.add_argument("gpu_json")
     ap.add_argument("--part", choices=("frobenius", "pnorm", "all"), default="all")
     ap.add_argument("--pa-log2", type=int, default=22, help="n of the oracle's A_p")
+    ap.add_argument("--ref-cache", default=None, help="JSON cache of the p-norm study's oracle values")
     args = ap.parse_args()
     with open(args.gpu_json) as f:
         g = json.load(f)
@@ -90,7 +108,7 @@ def main():
     if args.part in ("frobenius", "all") and g.get("seeds", 0) > 0:
         r.update(frobenius(g))
     if args.part in ("pnorm", "all") and g.get("pnorm_seeds", 0) > 0:
-        r["pnorm"] = pnorm(g, args.pa_log2)
+        r["pnorm"] = pnorm(g, args.pa_log2, args.ref_cache)
     print(json.dumps({"accuracy_study": r}), flush=True)
 
 
