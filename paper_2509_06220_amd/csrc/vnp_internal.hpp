@@ -1,7 +1,7 @@
 // Node objects evaluated by the tree kernels.  Each provides
-//   leaf(a, b):     the node on two raw elements (signs allowed), as the row levels' type R,
-//   row(u, v):      the node on the per-lane row levels (R; here R = T and row = node),
-//   row_root(r):    the map from a row tree's root to T (the identity here),
+//   leaf(a, b):     the node on two raw elements (signs allowed), as the tile levels' type R,
+//   row(u, v):      the node on the levels inside a tile (R; here R = T and row = node),
+//   row_root(r):    the map from a tile's root to T (the identity here),
 //   node(a, b):     the node on two non-negative partial norms above the rows,
 //   finish(r):      the map from the tree root to the result (identity for all nodes here).
 // Paper (Novakovic, arXiv 2509.06220): Frobenius node = hypot (Sect. 1, Eq. (hr));

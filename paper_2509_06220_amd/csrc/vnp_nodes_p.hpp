@@ -42,8 +42,8 @@
 // m = 0 (Q = 0) clears the high word of S: what is left is below 2^-1042, its square
 // vanishes, Z = 1, w = 2^(s - 1074) at most, and node(M, 0) = M exactly.
 //
-// This value form evaluates every node of binary32 and the levels above the per-lane rows of
-// binary64; the binary64 row levels carry logarithms instead (LpPair, below).
+// This value form evaluates every node of binary32 and the levels above the tiles of
+// binary64; inside a tile, binary64 carries logarithms instead (LpPair, below).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -230,7 +230,7 @@ __device__ __forceinline__ LpPair xshfl(LpPair v, int s) { return LpPair{__shfl_
 constexpr int LP_ZERO_E = -(1 << 30);
 constexpr int LP_INF_E = 1 << 28;
 constexpr int LP_NAN_E = 1 << 29;
-constexpr double LP_PAIR_MAX_IA = 0x1p20;  // largest 1/p of the logarithmic row levels
+constexpr double LP_PAIR_MAX_IA = 0x1p20;  // largest 1/p of the logarithmic tile levels
 
 // The common tail of the row node and the leaf: log2 M + (1/p) log2(1 + 2^y) as a pair,
 // for y = 128 p d <= 0 (y = 128 p d clamped; d <= 0 up to the table's rounding, which
@@ -300,7 +300,7 @@ __device__ __forceinline__ double lp_pair_value(LpPair v)
 
 // The evaluation part of the p node: 128 RN(p/2), s, RN(1/p) and the row-domain flag, with
 // every table read from LDS.  Device functions that are not inlined receive this part only
-// (node_eval).  Interface of the tree: leaf(a, b) and row(u, v) on the row levels' type R,
+// (node_eval).  Interface of the tree: leaf(a, b) and row(u, v) on the tile levels' type R,
 // row_root(r) back to T, node(a, b) on T above the rows.
 template <typename T>
 struct LpEval;
@@ -312,7 +312,7 @@ struct LpEval<double> {
     double hp128;  // 128 RN(p/2)
     double ia;     // RN(1/p)
     int sq;        // s: C = (Z^a')^(2^s)
-    int pair;      // row levels in the logarithmic domain (1/p <= 2^20)
+    int pair;      // tile levels in the logarithmic domain (1/p <= 2^20)
     __device__ LpPair leaf(double a, double b) const
     {
         if (!pair) return LpPair{lp_core<true>(a, b, hp128, sq), 0};
