@@ -298,10 +298,10 @@ __device__ __forceinline__ double lp_pair_value(LpPair v)
     return v.e >= LP_NAN_E ? __builtin_nan("") : r;
 }
 
-// The evaluation part of the p node: 128 RN(p/2), s, RN(1/p) and the row-domain flag, with
+// The evaluation part of the p node: 128 RN(p/2), s, RN(1/p) and the log-domain flag, with
 // every table read from LDS.  Device functions that are not inlined receive this part only
 // (node_eval).  Interface of the tree: leaf(a, b) and row(u, v) on the tile levels' type R,
-// row_root(r) back to T, node(a, b) on T above the rows.
+// row_root(r) back to T, node(a, b) on T above the tiles.
 template <typename T>
 struct LpEval;
 
