@@ -210,8 +210,8 @@ __device__ __forceinline__ double lp_core(double a, double b, double hp128, int 
 //   * node(v, 0) = v exactly: a zero operand gives S^2 = 0, (1 + S^2)/2 = 1/2, whose log2
 //     table entry (c_0 = 2, l_0 = 0) gives log2 = 0 exactly, and l + 0 keeps l and e; the
 //     zero padding of the tree is therefore exact.
-//   * +0 is e <= -2^29 (LP_ZERO_E = -2^30), +inf e in [2^27, 2^29) (LP_INF_E), NaN e >= 2^29
-//     (LP_NAN_E), each with l = 0, set by the leaves.  The row node orders such pairs like
+//   * +0 is e <= -2^29 (LP_ZERO_E = -2^30, with a finite l), +inf e in [2^27, 2^29)
+//     (LP_INF_E), NaN e >= 2^29 (LP_NAN_E), both with l = 0, set by the leaves.  The row node orders such pairs like
 //     the values they stand for (NaN above inf above every finite value above +0), and a
 //     level moves e by at most 1/p + 1, so the thirteen levels of a tile keep every class
 //     apart while 1/p <= 2^20 (for larger 1/p, i.e. p below about 9.5e-7, the node stays in the value
