@@ -27,8 +27,8 @@ mp.mp.dps = 60
 HERE = os.path.dirname(os.path.abspath(__file__))
 LOG_BITS = 10  # fraction bits of f in [1/2, 1) that pick the log2 table entry
 LOG_DEG = 3    # degree of g
-EXP_BITS = 7   # 2^y table: 2^EXP_BITS entries per octave
-EXP_DEG = 4    # degree of H
+EXP_BITS = 9   # 2^y table: 2^EXP_BITS entries per octave
+EXP_DEG = 3    # degree of H
 POW_BITS = 9   # fraction bits of Z in [1, 2) that pick the power table entry
 POW_TERMS = 5  # binomial terms b_1 .. b_POW_TERMS of (1 + t)^a'
 T_MAX = mp.mpf(2) ** -(LOG_BITS + 1) * mp.mpf("1.01")  # |t| bound of the reduced log argument, with margin
@@ -124,6 +124,7 @@ def main():
                  f"binomial series of {POW_TERMS} terms (first omitted term\n// <= 2^{mp.nstr(tb, 3)}).\n")
         fh.write("#pragma once\n\nnamespace vnp {\n\n")
         fh.write(f"constexpr int LP_LOG_BITS = {LOG_BITS};\nconstexpr int LP_EXP_BITS = {EXP_BITS};\n"
+                 f"constexpr int LP_EXP_DEG = {EXP_DEG};\n"
                  f"constexpr int LP_POW_BITS = {POW_BITS};\nconstexpr int LP_POW_TERMS = {POW_TERMS};\n")
         fh.write("static __constant__ double lp_log_src[(1 << LP_LOG_BITS) + 1][2] = {\n")
         for c, l in lrows:

@@ -13,9 +13,9 @@
 //   and l_j = log2(2 / c_j); log2 f + 1 = l_j + t g(t), t = fma(f, c_j, -1), -1.01 * 2^-11
 //   <= t <= 1.01 * 2^-10, g of degree 3, evaluated as fma(t, g, l_j).  Entry 0 is the
 //   interval's left end (c_0 = 2, l_0 = 0), so that f = 1/2 gives exactly 0.
-//   2^(y/128) for y = 128 (p/2) log2 Q: y = 128 k + j + u with integers k, j in [0, 128)
-//   and |u| <= 1/2 (rounding y to an integer by adding 1.5 * 2^52, whose low word then
-//   holds it), 2^(y/128) = 2^k T_j (1 + u H(u)), T_j = RN(2^(j/128)), H of degree 4.
+//   2^(y/N) for y = N (p/2) log2 Q, N = 2^LP_EXP_BITS = 512: y = N k + j + u with integers
+//   k, j in [0, N) and |u| <= 1/2 (rounding y to an integer by adding 1.5 * 2^52, whose low
+//   word then holds it), 2^(y/N) = 2^k T_j (1 + u H(u)), T_j = RN(2^(j/N)), H of degree 3.
 //   C = Z^a, a = RN(1/p), Z in [1, 2]: with a = a' 2^s, a' <= 2, C = (Z^a')^(2^s).  The top
 //   LP_POW_BITS fraction bits of Z pick c'_j = RN(512 / (512 + j)) (the reciprocal of the
 //   interval's left end), R_j = (1/c'_j)^a' and rho_j = R_j - 1 (both rounded from an
@@ -28,7 +28,7 @@
 // (Coefficients and tables: Chebyshev fits and 60-digit values written by lp_coeffs.py.)
 //
 // Errors: the log2 table values carry 2^-54 absolute and the two fma(t, g, l_j) 2^-54
-// each, g 2^-56.4 (absolute), 1 + u H(u) 2^-62.8 and T_j 2^-53 (relative); the binomial
+// each, g 2^-56.4 (absolute), 1 + u H(u) 2^-62.7 and T_j 2^-53 (relative); the binomial
 // series omits less than 2^-59.4.  An absolute error d in log2 Q changes C by at most
 // (ln 2 / 2) d relatively, whatever p is (the error of S^2 is weighted by
 // S^2 / (p (1 + S^2)) in C); each squaring doubles the relative error of Z^a', so p < 1/2
@@ -66,7 +66,7 @@ constexpr int LP_B_N = 8;  // binomial coefficient slots (LP_POW_TERMS used)
 constexpr double LP_RHO0 = 0x1p-1074;  // rho_0 (see above)
 
 // The tables in LDS, one copy per block, filled by lp_table_fill at kernel entry, in one
-// arena: the log2 table first (1025 entries), then 2^(j/128), the power table and the
+// arena: the log2 table first (1025 entries), then 2^(j/N), the power table and the
 // coefficients.  log2_p1 indexes with the exponent's low bit, so the mantissa of a NaN
 // (from two NaN operands, whose result is replaced) picks an index in [1024, 2048): the
 // arena spans more than 2048 log2 entries, so that read stays inside it.
@@ -76,7 +76,7 @@ struct PowEntry {
 // Polynomial coefficients: g (4), H (5), then the binomial coefficients b_1 .. b_5 (and
 // zeros).  Read at one address in all lanes: as scalar operands they would exhaust the
 // scalar registers, and two scalar operands of one fma cost an extra vector move.
-constexpr int LP_G_OFF = 0, LP_H_OFF = 4, LP_BC_OFF = 9;
+constexpr int LP_G_OFF = 0, LP_H_OFF = 4, LP_BC_OFF = LP_H_OFF + LP_EXP_DEG + 1;
 constexpr int LP_LOG_BYTES = (LP_LOG_N + 1) * 16;
 constexpr int LP_EXP_AT = LP_LOG_BYTES;
 constexpr int LP_POW_AT = LP_EXP_AT + LP_EXP_N * 8;
@@ -110,7 +110,7 @@ __device__ __forceinline__ void lp_table_fill(const double *rr, const double *b)
         pt[i] = PowEntry{rr[i], rr[LP_POW_N + i], lp_pow_src[i], 0.0};
     double *cf = lp_coef_lds();
     if (threadIdx.x < 4) cf[LP_G_OFF + threadIdx.x] = lp_log_g[threadIdx.x];
-    if (threadIdx.x < 5) cf[LP_H_OFF + threadIdx.x] = lp_exp_h[threadIdx.x];
+    if (threadIdx.x <= LP_EXP_DEG) cf[LP_H_OFF + threadIdx.x] = lp_exp_h[threadIdx.x];
     if (threadIdx.x < LP_B_N) cf[LP_BC_OFF + threadIdx.x] = b[threadIdx.x];
     __syncthreads();
 }
@@ -128,7 +128,11 @@ __device__ __forceinline__ double log2_p1(double f)
     return __builtin_fma(t, g, e.y);
 }
 
-// 2^(y/128) for y in [-2100 * 128, 0] (y = +inf gives NaN, which the caller absorbs).
+// Lower clamp of y (2^(y/N) underflows to +0 well above it; |y| < 2^31 for the rounding).
+constexpr double LP_Y_MIN = -2100.0 * LP_EXP_N;
+
+// 2^(y/N), N = 2^LP_EXP_BITS, for y in [LP_Y_MIN, 0] (y = +inf gives NaN, which the caller
+// absorbs).
 __device__ __forceinline__ double exp2_tab(double y)
 {
     // y + 1.5 * 2^52 holds round(y) in its low word (|y| < 2^31)
@@ -139,7 +143,7 @@ __device__ __forceinline__ double exp2_tab(double y)
     const double *Hc = lp_coef_lds() + LP_H_OFF;
     double h = Hc[0];
 #pragma unroll
-    for (int i = 1; i < 5; ++i) h = __builtin_fma(h, u, Hc[i]);
+    for (int i = 1; i <= LP_EXP_DEG; ++i) h = __builtin_fma(h, u, Hc[i]);
     return __builtin_amdgcn_ldexp(__builtin_fma(T, u * h, T), k >> LP_EXP_BITS);
 }
 
@@ -162,9 +166,9 @@ __device__ __forceinline__ double pow_z_m1(double Z, int sq)
 }
 
 // The node on |a|, |b| (ABS: a leaf, whose operands carry signs; otherwise a, b >= 0),
-// NaN and infinities as above; hp128 = 128 RN(p/2) (exact).
+// NaN and infinities as above; hpy = N RN(p/2) (exact), N = 2^LP_EXP_BITS.
 template <bool ABS>
-__device__ __forceinline__ double lp_core(double a, double b, double hp128, int sq)
+__device__ __forceinline__ double lp_core(double a, double b, double hpy, int sq)
 {
     // v_max_f64 / v_min_f64 directly, the absolute values as operand modifiers: as fmax /
     // fmin the compiler first canonicalizes each operand (two more instructions), which only
@@ -182,7 +186,7 @@ __device__ __forceinline__ double lp_core(double a, double b, double hp128, int 
     const double hm = log2_p1(__builtin_amdgcn_frexp_mant(m));
     const int e = __builtin_amdgcn_frexp_exp(m) - __builtin_amdgcn_frexp_exp(M);
     const double lq = (double)e + (hm - hM);  // log2 Q <= 0
-    const double S = exp2_tab(__builtin_fmax(hp128 * lq, -2100.0 * 128));
+    const double S = exp2_tab(__builtin_fmax(hpy * lq, LP_Y_MIN));
     const uint64_t sb = (uint64_t)__double_as_longlong(S);
     const uint32_t shi = m > 0.0 ? (uint32_t)(sb >> 32) : 0u;  // m = 0: S below 2^-1042
     const double Sm = __longlong_as_double((long long)(((uint64_t)shi << 32) | (sb & 0xffffffffu)));
@@ -201,7 +205,7 @@ __device__ __forceinline__ double lp_core(double a, double b, double hp128, int 
 //     log2 node = log2 M + (1/p) log2(1 + 2^(p d)),  d = log2 m - log2 M = -|log2 a - log2 b|,
 // with 2^(p d) = S^2 = Q^(2 RN(p/2)) and 1/p = RN(1/p) (the exponents rounded once, Sect. 4).
 // An internal row node therefore needs no logarithm of its operands and no power: one 2^y
-// (the table above, y = 128 p d), one log2(1 + S^2) (the log2 table at (1 + S^2)/2, whose
+// (the table above, y = N p d), one log2(1 + S^2) (the log2 table at (1 + S^2)/2, whose
 // rounding is that of Z = fma(S, S, 1)), and an fma; a leaf takes the logarithms of its two
 // elements first.  The tile root goes back to a value, 2^l scaled by 2^e, and the levels
 // above (tiles, runs, blocks) use the value node lp_core.
@@ -233,11 +237,11 @@ constexpr int LP_NAN_E = 1 << 29;
 constexpr double LP_PAIR_MAX_IA = 0x1p20;  // largest 1/p of the logarithmic tile levels
 
 // The common tail of the row node and the leaf: log2 M + (1/p) log2(1 + 2^y) as a pair,
-// for y = 128 p d <= 0 (y = 128 p d clamped; d <= 0 up to the table's rounding, which
+// for y = N p d <= 0 (y = N p d clamped; d <= 0 up to the table's rounding, which
 // -|d| absorbs).
-__device__ __forceinline__ LpPair lp_pair_tail(double d, double lM, int eM, double p128, double ia)
+__device__ __forceinline__ LpPair lp_pair_tail(double d, double lM, int eM, double py, double ia)
 {
-    const double y = __builtin_fmax(-p128 * __builtin_fabs(d), -2100.0 * 128);
+    const double y = __builtin_fmax(-py * __builtin_fabs(d), LP_Y_MIN);
     const double S2 = exp2_tab(y);
     // (1 + S^2)/2 in [1/2, 1] (S^2 <= 1 since y <= 0)
     const double lr = __builtin_fma(ia, log2_p1(__builtin_fma(S2, 0.5, 0.5)), lM);  // >= 0
@@ -245,11 +249,11 @@ __device__ __forceinline__ LpPair lp_pair_tail(double d, double lM, int eM, doub
 }
 
 // Row node on two pairs.
-__device__ __forceinline__ LpPair lp_pair_node(LpPair a, LpPair b, double p128, double ia)
+__device__ __forceinline__ LpPair lp_pair_node(LpPair a, LpPair b, double py, double ia)
 {
     const double d = (double)(a.e - b.e) + (a.l - b.l);  // log2 a - log2 b
     const bool ga = d >= 0.0;
-    return lp_pair_tail(d, ga ? a.l : b.l, ga ? a.e : b.e, p128, ia);
+    return lp_pair_tail(d, ga ? a.l : b.l, ga ? a.e : b.e, py, ia);
 }
 
 // Leaf on two elements (signs allowed): log2 |a|, log2 |b| from the log2 table, then the
@@ -261,7 +265,7 @@ __device__ __forceinline__ LpPair lp_pair_node(LpPair a, LpPair b, double p128, 
 //   M = 0:     +0, e = LP_ZERO_E (with l from the same lM, a finite value);
 //   an infinite or NaN operand: l = 0 and the class's e (the logarithm of inf is not
 //   finite).
-__device__ __forceinline__ LpPair lp_pair_leaf(double a, double b, double p128, double ia)
+__device__ __forceinline__ LpPair lp_pair_leaf(double a, double b, double py, double ia)
 {
     double M, m;
     asm("v_max_f64 %0, |%1|, |%2|" : "=v"(M) : "v"(a), "v"(b));
@@ -271,7 +275,7 @@ __device__ __forceinline__ LpPair lp_pair_leaf(double a, double b, double p128, 
     // frexp's exponents are one above those of the mantissa in [1, 2); equal offsets cancel
     const int eM = __builtin_amdgcn_frexp_exp(M);
     const int em = __builtin_amdgcn_frexp_exp(m);
-    LpPair r = lp_pair_tail((double)(em - eM) + (lm - lM), lM, eM - 1, p128, ia);
+    LpPair r = lp_pair_tail((double)(em - eM) + (lm - lM), lM, eM - 1, py, ia);
     const bool nan = __builtin_isunordered(a, b);
     const bool inf = __builtin_isinf(M);
     const bool zero = !(m > 0.0);
@@ -282,10 +286,10 @@ __device__ __forceinline__ LpPair lp_pair_leaf(double a, double b, double p128, 
     return r;
 }
 
-// The value of a pair: 2^l from the 2^y table (y = 128 l in [0, 128)), scaled by 2^e.
+// The value of a pair: 2^l from the 2^y table (y = N l in [0, N)), scaled by 2^e.
 __device__ __forceinline__ double lp_pair_value(LpPair v)
 {
-    const double y = v.l * 128.0;
+    const double y = v.l * (double)LP_EXP_N;
     const double big = y + 0x1.8p52;
     const int k = (int)(uint32_t)(uint64_t)__double_as_longlong(big);
     const double u = y - (big - 0x1.8p52);
@@ -293,12 +297,12 @@ __device__ __forceinline__ double lp_pair_value(LpPair v)
     const double *Hc = lp_coef_lds() + LP_H_OFF;
     double h = Hc[0];
 #pragma unroll
-    for (int i = 1; i < 5; ++i) h = __builtin_fma(h, u, Hc[i]);
+    for (int i = 1; i <= LP_EXP_DEG; ++i) h = __builtin_fma(h, u, Hc[i]);
     const double r = __builtin_amdgcn_ldexp(__builtin_fma(T, u * h, T), (k >> LP_EXP_BITS) + v.e);
     return v.e >= LP_NAN_E ? __builtin_nan("") : r;
 }
 
-// The evaluation part of the p node: 128 RN(p/2), s, RN(1/p) and the log-domain flag, with
+// The evaluation part of the p node: N RN(p/2), s, RN(1/p) and the log-domain flag, with
 // every table read from LDS.  Device functions that are not inlined receive this part only
 // (node_eval).  Interface of the tree: leaf(a, b) and row(u, v) on the tile levels' type R,
 // row_root(r) back to T, node(a, b) on T above the tiles.
@@ -309,22 +313,22 @@ template <>
 struct LpEval<double> {
     using T = double;
     using R = LpPair;
-    double hp128;  // 128 RN(p/2)
+    double hpy;  // N RN(p/2), N = 2^LP_EXP_BITS
     double ia;     // RN(1/p)
     int sq;        // s: C = (Z^a')^(2^s)
     int pair;      // tile levels in the logarithmic domain (1/p <= 2^20)
     __device__ LpPair leaf(double a, double b) const
     {
-        if (!pair) return LpPair{lp_core<true>(a, b, hp128, sq), 0};
-        return lp_pair_leaf(a, b, 2.0 * hp128, ia);
+        if (!pair) return LpPair{lp_core<true>(a, b, hpy, sq), 0};
+        return lp_pair_leaf(a, b, 2.0 * hpy, ia);
     }
     __device__ LpPair row(LpPair a, LpPair b) const
     {
-        if (!pair) return LpPair{lp_core<false>(a.l, b.l, hp128, sq), 0};
-        return lp_pair_node(a, b, 2.0 * hp128, ia);
+        if (!pair) return LpPair{lp_core<false>(a.l, b.l, hpy, sq), 0};
+        return lp_pair_node(a, b, 2.0 * hpy, ia);
     }
     __device__ double row_root(LpPair r) const { return pair ? lp_pair_value(r) : r.l; }
-    __device__ double node(double a, double b) const { return lp_core<false>(a, b, hp128, sq); }
+    __device__ double node(double a, double b) const { return lp_core<false>(a, b, hpy, sq); }
     __device__ double finish(double r) const { return r; }
 };
 
@@ -332,15 +336,15 @@ template <>
 struct LpEval<float> {
     using T = float;
     using R = float;
-    double hp128;  // 128 RN32(p/2)
+    double hpy;  // N RN32(p/2)
     double ia;     // unused (binary32 keeps the value node on every level)
     int sq;
     int pair;
     __device__ float leaf(float a, float b) const
     {
-        return (float)lp_core<true>((double)a, (double)b, hp128, sq);
+        return (float)lp_core<true>((double)a, (double)b, hpy, sq);
     }
-    __device__ float node(float a, float b) const { return (float)lp_core<false>((double)a, (double)b, hp128, sq); }
+    __device__ float node(float a, float b) const { return (float)lp_core<false>((double)a, (double)b, hpy, sq); }
     __device__ float row(float a, float b) const { return node(a, b); }
     __device__ float row_root(float r) const { return r; }
     __device__ float finish(float r) const { return r; }
@@ -359,7 +363,7 @@ struct LpNode : LpEval<T> {
 template <typename T>
 __host__ __device__ inline LpEval<T> node_eval(const LpNode<T> &nd)
 {
-    return LpEval<T>{nd.hp128, nd.ia, nd.sq, nd.pair};
+    return LpEval<T>{nd.hpy, nd.ia, nd.sq, nd.pair};
 }
 
 // Kernel-entry hook of the nodes: the p node fills its tables (the other nodes have
@@ -435,7 +439,7 @@ inline int lp_node(double half_p, double a, LpNode<T> *out)
         }
         it = c.map.emplace(key, en).first;
     }
-    out->hp128 = half_p * 128.0;
+    out->hpy = half_p * (double)LP_EXP_N;
     out->ia = a;
     out->sq = it->second.sq;
     out->pair = sizeof(T) == 8 && a <= LP_PAIR_MAX_IA;
