@@ -215,16 +215,17 @@ __device__ __forceinline__ double lp_core(double a, double b, double hpy, int sq
 //     table entry (c_0 = 2, l_0 = 0) gives log2 = 0 exactly, and l + 0 keeps l and e; the
 //     zero padding of the tree is therefore exact.
 //   * +0 is e <= -2^29 (LP_ZERO_E = -2^30, with a finite l), +inf e in [2^27, 2^29)
-//     (LP_INF_E), NaN e >= 2^29 (LP_NAN_E), both with l = 0, set by the leaves.  The row node orders such pairs like
-//     the values they stand for (NaN above inf above every finite value above +0), and a
-//     level moves e by at most 1/p + 1, so the thirteen levels of a tile keep every class
-//     apart while 1/p <= 2^20 (for larger 1/p, i.e. p below about 9.5e-7, the node stays in the value
-//     domain: the uniform flag `pair`).  The conversion to a value maps e beyond the
-//     binary64 range to +inf or +0 by ldexp, and NaN pairs to NaN.
+//     (LP_INF_E), NaN e >= 2^29 (LP_NAN_E), both with l = 0, set by the leaves.  The row
+//     node orders such pairs like the values they stand for (NaN above inf above every
+//     finite value above +0), and a level moves e by at most 1/p + 1, so the thirteen
+//     levels of a tile keep every class apart while 1/p <= 2^20 (for larger 1/p, i.e. p
+//     below about 9.5e-7, the node stays in the value domain: the uniform flag `pair`).
+//     The conversion to a value maps e beyond the binary64 range to +inf or +0 by ldexp,
+//     and NaN pairs to NaN.
 //   * Errors per row node: the two table functions (2^-54 each, absolute in log2), the
-//     rounding of (1 + S^2)/2, which reaches log2 multiplied by 1/p as in Sect. 4's C = Z^(1/p),
-//     and the rounding of l (2^-54 absolute); in the value these are relative errors times
-//     ln 2.
+//     rounding of (1 + S^2)/2, which reaches log2 multiplied by 1/p as in Sect. 4's
+//     C = Z^(1/p), and the rounding of l (2^-54 absolute); in the value these are relative
+//     errors times ln 2.
 struct LpPair {
     double l;  // in [0, 1)
     int e;
